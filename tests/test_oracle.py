@@ -1,0 +1,395 @@
+"""Pins of the CPU oracle against the paper and the mathematics (no GPU).
+
+Each test checks the oracle against something other than itself: a value
+the paper states, a closed form, an invariant of the method, or the
+pure-Python brute force (a differently structured statement of the same
+definitions) on tiny inputs.
+"""
+
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import brute
+from paper_2212_00488_amd.synth import make_pair, textured_shift_pair
+
+P = oracle.Params()
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def rng_img(rng, H, W, lo=0, hi=256):
+    return rng.integers(lo, hi, size=(H, W), dtype=np.uint8)
+
+
+def as_np(nested, dtype):
+    return np.array(nested, dtype=dtype)
+
+
+# ------------------------------------------------------------- cost tables
+
+def test_lut_bounds_of_one_minus_exp():
+    """Eq. 4-5: S(1 - e^-t) lies in [S(t - t^2/2), S t] and below S; the
+    tables are that value rounded, so monotone, 0 at 0, within the bounds."""
+    ad, mc = oracle.lut(P)
+    S = P.cost_scale
+    for table, denom, n in ((ad, 255.0 * P.lambda_ad, 256), (mc, P.lambda_mc, 7)):
+        assert table[0] == 0
+        assert np.all(np.diff(table.astype(int)) >= 0)
+        for a in range(n):
+            t = a / denom
+            assert S * (t - t * t / 2) - 0.5 <= table[a] <= min(S * t, S) + 0.5
+            assert table[a] <= S * (1 - math.exp(-t)) + 0.5 + 1e-9
+
+
+def test_lut_matches_brute_recomputation():
+    ad, mc = oracle.lut(P)
+    bad, bmc = brute.tables(P.lambda_ad, P.lambda_mc, P.cost_scale)
+    assert ad.tolist() == bad and mc.tolist() == bmc
+
+
+def test_lut_saturation_reading():
+    """lambda_AD = 0.3 (Sec. V) on [0,1] brightness: the AD cost keeps growing
+    over the whole 0..255 range (it would saturate at 2 grey levels on 0..255)."""
+    ad, _ = oracle.lut(P)
+    assert len(set(ad.tolist())) > 200
+    assert ad[255] < P.cost_scale
+
+
+# ------------------------------------------------------- a1 gray + downscale
+
+def test_gray_of_gray_pixels_is_identity():
+    c = np.arange(256, dtype=np.uint8)
+    rgb = np.stack([c, c, c], axis=-1).reshape(16, 16, 3)
+    assert np.array_equal(oracle.gray(rgb), c.reshape(16, 16))
+
+
+def test_gray_and_downscale_match_brute():
+    rng = np.random.default_rng(5)
+    for (H, W) in ((6, 8), (7, 9), (2, 3)):
+        rgb = rng.integers(0, 256, size=(H, W, 3), dtype=np.uint8)
+        g = oracle.gray(rgb)
+        assert np.array_equal(g, as_np(brute.gray(rgb.tolist()), np.uint8))
+        assert np.array_equal(oracle.downscale(g), as_np(brute.downscale(g.tolist()), np.uint8))
+
+
+def test_downscale_constant_and_shape():
+    for (H, W) in ((10, 14), (11, 13)):
+        g = np.full((H, W), 77, np.uint8)
+        h = oracle.downscale(g)
+        assert h.shape == ((H + 1) // 2, (W + 1) // 2)
+        assert np.all(h == 77)
+
+
+def test_downscale_commutes_with_even_shift():
+    """Eq. 2 with K = 2: shifting the full-res image by 2k shifts the
+    half-res image by k away from the clamped borders."""
+    rng = np.random.default_rng(6)
+    g = rng_img(rng, 20, 40)
+    k = 3
+    gs = np.zeros_like(g)
+    gs[:, : 40 - 2 * k] = g[:, 2 * k:]
+    h, hs = oracle.downscale(g), oracle.downscale(gs)
+    assert np.array_equal(hs[:, 1: 20 - k - 1], h[:, 1 + k: 20 - 1])
+
+
+# ------------------------------------------------------------- a2 census
+
+def test_census_hand_example():
+    """Six neighbours in three rows, bit k = neighbour < centre, LSB first:
+    (-1,-1) (+1,-1) (-2,0) (+2,0) (-1,+1) (+1,+1)."""
+    h = np.array([[0, 9, 0, 50, 0],
+                  [30, 0, 40, 0, 60],
+                  [0, 10, 0, 70, 0]], np.uint8)
+    c = oracle.census(h)
+    # centre (2,1) = 40: (1,0)=9<40 b0, (3,0)=50 no, (0,1)=30<40 b2,
+    # (4,1)=60 no, (1,2)=10<40 b4, (3,2)=70 no
+    assert c[1, 2] == 0b010101
+
+
+def test_census_flat_and_brute():
+    assert np.all(oracle.census(np.full((5, 7), 9, np.uint8)) == 0)
+    rng = np.random.default_rng(7)
+    for (Y, X) in ((5, 7), (1, 3), (6, 2)):
+        h = rng_img(rng, Y, X)
+        assert np.array_equal(oracle.census(h), as_np(brute.census(h.tolist()), np.uint8))
+
+
+# --------------------------------------------------------------- a2 arms
+
+def load_arms_example():
+    rows, meta = [], {}
+    with open(os.path.join(GOLDEN, "arms_example.txt")) as f:
+        for line in f:
+            if line.startswith("# centre:") or line.startswith("# expect:"):
+                for kv in line[9:].split():
+                    k, v = kv.split("=")
+                    meta[k] = int(v)
+            elif not line.startswith("#") and line.strip():
+                rows.append([int(v) for v in line.split()])
+    return np.array(rows, np.uint8), meta
+
+
+def test_arms_paper_worked_example():
+    """Sec. III-C: seven similar pixels on the row give m = n = 3, nine on
+    the column give M = N = 4 (arms exclude the centre)."""
+    img, meta = load_arms_example()
+    a = oracle.arms(img, P)
+    assert tuple(a[meta["y"], meta["x"]]) == (meta["m"], meta["n"], meta["M"], meta["N"])
+
+
+def test_arms_never_cross_an_edge():
+    """Every pixel inside an arm is within delta of the centre; the next one,
+    when inside the cap and the image, is not."""
+    pair = make_pair(64, 48, 16, segments=4, seed=11)
+    h = oracle.downscale(oracle.gray(pair.left))
+    a = oracle.arms(h, P).astype(int)
+    Y, X = h.shape
+    hi = h.astype(int)
+    for y in range(Y):
+        for x in range(X):
+            c = hi[y, x]
+            for k, (dx, dy, cap) in enumerate(((-1, 0, P.arm_x), (1, 0, P.arm_x),
+                                               (0, -1, P.arm_y), (0, 1, P.arm_y))):
+                L = a[y, x, k]
+                for t in range(1, L + 1):
+                    assert abs(hi[y + dy * t, x + dx * t] - c) < P.color_delta
+                nx, ny = x + dx * (L + 1), y + dy * (L + 1)
+                if L < cap and 0 <= nx < X and 0 <= ny < Y:
+                    assert abs(hi[ny, nx] - c) >= P.color_delta
+
+
+def test_arms_flat_image_reach_cap_or_border():
+    Y, X = 40, 70
+    a = oracle.arms(np.full((Y, X), 5, np.uint8), P).astype(int)
+    xs, ys = np.meshgrid(np.arange(X), np.arange(Y))
+    assert np.array_equal(a[..., 0], np.minimum(P.arm_x, xs))
+    assert np.array_equal(a[..., 1], np.minimum(P.arm_x, X - 1 - xs))
+    assert np.array_equal(a[..., 2], np.minimum(P.arm_y, ys))
+    assert np.array_equal(a[..., 3], np.minimum(P.arm_y, Y - 1 - ys))
+
+
+def test_arms_match_brute():
+    rng = np.random.default_rng(8)
+    for (Y, X, lo, hi) in ((9, 11, 90, 120), (7, 5, 0, 256)):
+        h = rng_img(rng, Y, X, lo, hi)
+        got = oracle.arms(h, oracle.Params(arm_x=3, arm_y=4))
+        exp = brute.arms(h.tolist(), 13, 3, 4)
+        assert np.array_equal(got, as_np(exp, np.uint8))
+
+
+# ------------------------------------------------------ a3 costs (Eq. 3-6)
+
+def _half_planes(pair):
+    hl = oracle.downscale(oracle.gray(pair[0]))
+    hr = oracle.downscale(oracle.gray(pair[1]))
+    return hl, hr, oracle.census(hl), oracle.census(hr)
+
+
+def test_cost_left_matches_brute_and_right_identity():
+    """Eq. 3-5 against the brute force; Eq. 6 (C^R(x) = C^L(x+d)) against a
+    right-based cost computed directly from R(x) and L(x+d)."""
+    p = make_pair(30, 20, 12, segments=3, seed=3)
+    hl, hr, cl, cr = _half_planes((p.left, p.right))
+    tad, tmc = brute.tables(P.lambda_ad, P.lambda_mc, P.cost_scale)
+    Y, X = hl.shape
+    cmax = tad[255] + tmc[6]
+    L = [v.tolist() for v in (hl, hr, cl, cr)]
+    for d in (0, 1, 4, X - 1, X + 2):
+        cL = oracle.cost_left(hl, hr, cl, cr, d, P)
+        cR = oracle.cost_right_from_left(cL, d, cmax)
+        expL = [[brute.cost_l(*L, x, y, d, tad, tmc) for x in range(X)] for y in range(Y)]
+        expR = [[brute.cost_r(*L, x, y, d, tad, tmc) for x in range(X)] for y in range(Y)]
+        assert np.array_equal(cL, as_np(expL, np.uint16))
+        assert np.array_equal(cR, as_np(expR, np.uint16))
+
+
+# ------------------------------------------------ a4/a5 aggregation (Eq. 7-8)
+
+def test_aggregation_equals_cross_region_sum():
+    rng = np.random.default_rng(9)
+    Y, X = 9, 12
+    h = rng_img(rng, Y, X, 80, 110)
+    a = oracle.arms(h, oracle.Params(arm_x=4, arm_y=3))
+    cost = rng.integers(0, 1937, size=(Y, X)).astype(np.uint16)
+    ca = oracle.agg_y(oracle.agg_x(cost, a), a)
+    al = a.tolist()
+    fn = lambda x, y, d: int(cost[y, x])
+    exp = [[brute.aggregate(fn, al, x, y, 0) for x in range(X)] for y in range(Y)]
+    assert np.array_equal(ca, as_np(exp, np.uint32))
+
+
+def test_aggregation_of_constant_cost():
+    """A constant cost c aggregates to c times the number of pixels of the
+    cross region, sum over s in [-M, N] of (m + n + 1) of row y+s."""
+    pair = make_pair(48, 36, 8, segments=3, seed=12)
+    h = oracle.downscale(oracle.gray(pair.left))
+    a = oracle.arms(h, P).astype(np.int64)
+    Y, X = h.shape
+    c = 37
+    ca = oracle.agg_y(oracle.agg_x(np.full((Y, X), c, np.uint16), a.astype(np.uint8)),
+                      a.astype(np.uint8))
+    width = a[..., 0] + a[..., 1] + 1
+    for y in range(Y):
+        for x in range(X):
+            M, N = a[y, x, 2], a[y, x, 3]
+            assert ca[y, x] == c * width[y - M: y + N + 1, x].sum()
+
+
+# ------------------------------------------- whole path vs brute force (tiny)
+
+CASES = [(12, 10, 6, 1), (13, 9, 5, 2), (16, 12, 8, 3), (7, 4, 3, 4), (20, 6, 12, 5)]
+
+
+@pytest.mark.parametrize("W,H,dmax,seed", CASES)
+def test_whole_path_matches_brute(W, H, dmax, seed):
+    p = make_pair(W, H, dmax, segments=3, seed=seed)
+    q = oracle.Params(arm_x=4, arm_y=3)
+    got = oracle.disparity(p.left, p.right, dmax, q)
+    exp = brute.disparity(p.left.tolist(), p.right.tolist(), dmax, q.lambda_ad, q.lambda_mc,
+                          q.cost_scale, q.color_delta, q.arm_x, q.arm_y, q.fill_T)
+    for k, dt in (("half_l", np.uint8), ("half_r", np.uint8), ("census_l", np.uint8),
+                  ("census_r", np.uint8), ("arms_l", np.uint8), ("arms_r", np.uint8),
+                  ("disp_l", np.int16), ("disp_r", np.int16), ("min_l", np.uint32),
+                  ("min_r", np.uint32), ("gcp", np.uint8), ("median", np.int16),
+                  ("filled", np.int16), ("out", np.int16)):
+        assert np.array_equal(got[k], as_np(exp[k], dt)), k
+
+
+def test_whole_path_default_arms_matches_brute():
+    p = make_pair(18, 14, 6, segments=2, seed=21)
+    got = oracle.disparity(p.left, p.right, 6, P)
+    exp = brute.disparity(p.left.tolist(), p.right.tolist(), 6, P.lambda_ad, P.lambda_mc,
+                          P.cost_scale, P.color_delta, P.arm_x, P.arm_y, P.fill_T)
+    for k in ("disp_l", "disp_r", "min_l", "min_r", "out"):
+        assert np.array_equal(got[k], np.array(exp[k])), k
+
+
+# ------------------------------------------------ constant-shift invariants
+
+@pytest.mark.parametrize("k", [0, 3, 7])
+def test_constant_shift_pair_returns_the_shift(k):
+    """R(x) = L(x + 2k) on a noise texture.  Away from the borders the cost at
+    d = k is exactly 0 over the whole cross region, so the minimum aggregate
+    is 0 and D^L <= k (smallest d wins).  Another d can only win where its
+    aggregate is 0 too (a tiny support region matching by chance), which the
+    test confirms by recomputing that plane.  On rows free of such chance
+    matches every interior pixel is a GCP and the output is 2k."""
+    W, H = 160, 40
+    left, right = textured_shift_pair(W, H, 2 * k, seed=30 + k)
+    r = oracle.disparity(left, right, 2 * 12, P)
+    X = W // 2
+    lo, hi = k + 26, X - k - 26
+    dl, dr = r["disp_l"], r["disp_r"]
+    assert np.all(r["min_l"][:, lo:hi] == 0) and np.all(dl[:, lo:hi] <= k)
+    assert np.all(r["min_r"][:, lo - k:hi - k] == 0) and np.all(dr[:, lo - k:hi - k] <= k)
+    hl, hr, cl, cr = r["half_l"], r["half_r"], r["census_l"], r["census_r"]
+    for y, x in np.argwhere(dl[:, lo:hi] != k):
+        d = int(dl[y, lo + x])
+        ca = oracle.agg_y(oracle.agg_x(oracle.cost_left(hl, hr, cl, cr, d, P), r["arms_l"]),
+                          r["arms_l"])
+        assert ca[y, lo + x] == 0
+    assert np.mean(dl[:, lo:hi] == k) > 0.99 and np.mean(dr[:, lo - k:hi - k] == k) > 0.99
+    clean = [y for y in range(1, dl.shape[0] - 1)
+             if np.all(dl[y - 1:y + 2, lo:hi] == k) and np.all(dr[y - 1:y + 2, lo - k:hi - k] == k)]
+    assert len(clean) > dl.shape[0] // 2
+    for y in clean:
+        assert np.all(r["gcp"][y, lo:hi] == 1)
+        assert np.all(r["median"][y, lo + 1:hi - 1] == k)
+        assert np.all(r["filled"][y, lo + 1:hi - 1] == k)
+        assert np.all(r["out"][2 * y, 2 * lo + 4: 2 * hi - 4] == 2 * k)
+
+
+# ------------------------------------------------ a6-a8 refinement pieces
+
+def test_crosscheck_definition_and_brute():
+    rng = np.random.default_rng(13)
+    dl = rng.integers(0, 4, size=(6, 10)).astype(np.int16)
+    dr = rng.integers(0, 4, size=(6, 10)).astype(np.int16)
+    assert np.array_equal(oracle.crosscheck(dl, dr),
+                          as_np(brute.crosscheck(dl.tolist(), dr.tolist()), np.uint8))
+    assert np.all(oracle.crosscheck(np.full((3, 5), 2, np.int16),
+                                    np.full((3, 5), 2, np.int16))[:, 2:] == 1)
+    assert np.all(oracle.crosscheck(np.full((3, 5), 2, np.int16),
+                                    np.full((3, 5), 2, np.int16))[:, :2] == 0)
+
+
+def test_median_is_the_fifth_order_statistic():
+    rng = np.random.default_rng(14)
+    d = rng.integers(0, 60, size=(9, 11)).astype(np.int16)
+    m = oracle.median(d)
+    Y, X = d.shape
+    for y in range(Y):
+        for x in range(X):
+            win = [d[min(max(y + j, 0), Y - 1), min(max(x + i, 0), X - 1)]
+                   for j in (-1, 0, 1) for i in (-1, 0, 1)]
+            assert m[y, x] == int(np.median(win))
+    assert np.all(oracle.median(np.full((4, 4), 9, np.int16)) == 9)
+
+
+def test_fill_all_gcp_keeps_median():
+    rng = np.random.default_rng(15)
+    med = rng.integers(0, 50, size=(5, 9)).astype(np.int16)
+    hl = rng_img(rng, 5, 9)
+    assert np.array_equal(oracle.fill(med, np.ones((5, 9), np.uint8), hl, 3), med)
+
+
+def test_fill_linear_ramp_and_step():
+    """Sec. III-E: between GCPs whose disparities differ by at most T the
+    fill is the straight line from the left value to the right one; across a
+    larger step it copies the side of closer brightness."""
+    X = 9
+    med = np.array([[10, 0, 0, 0, 0, 0, 0, 0, 13]], np.int16)
+    gcp = np.array([[1, 0, 0, 0, 0, 0, 0, 0, 1]], np.uint8)
+    hl = np.zeros((1, X), np.uint8)
+    out = oracle.fill(med, gcp, hl, 3)
+    exp = [math.floor(10 + 3 * i / 8 + 0.5) for i in range(X)]
+    assert out[0].tolist() == exp
+    med = np.array([[10, 0, 0, 30]], np.int16)
+    gcp = np.array([[1, 0, 0, 1]], np.uint8)
+    hl = np.array([[50, 52, 90, 95]], np.uint8)
+    assert oracle.fill(med, gcp, hl, 3)[0].tolist() == [10, 10, 30, 30]
+    hl = np.array([[50, 70, 70, 90]], np.uint8)     # equal distance: right side
+    assert oracle.fill(med, gcp, hl, 3)[0].tolist() == [10, 30, 30, 30]
+
+
+def test_fill_one_sided_and_empty_rows():
+    med = np.array([[0, 7, 0, 0], [0, 0, 0, 0]], np.int16)
+    gcp = np.array([[0, 1, 0, 0], [0, 0, 0, 0]], np.uint8)
+    out = oracle.fill(med, gcp, np.zeros((2, 4), np.uint8), 3)
+    assert out.tolist() == [[7, 7, 7, 7], [0, 0, 0, 0]]
+
+
+def test_fill_matches_brute():
+    rng = np.random.default_rng(16)
+    med = rng.integers(0, 20, size=(6, 15)).astype(np.int16)
+    gcp = (rng.random((6, 15)) < 0.4).astype(np.uint8)
+    hl = rng_img(rng, 6, 15)
+    exp = brute.fill(med.tolist(), gcp.tolist(), hl.tolist(), 3)
+    assert np.array_equal(oracle.fill(med, gcp, hl, 3), as_np(exp, np.int16))
+
+
+def test_upscale_constant_and_brute():
+    g = np.random.default_rng(17).integers(0, 256, size=(9, 13)).astype(np.uint8)
+    k = np.full((5, 7), 6, np.int16)
+    assert np.all(oracle.upscale(k, g, 3) == 12)
+    rng = np.random.default_rng(18)
+    for (H, W) in ((9, 13), (10, 12)):
+        g = rng_img(rng, H, W)
+        dp = rng.integers(0, 15, size=((H + 1) // 2, (W + 1) // 2)).astype(np.int16)
+        exp = brute.upscale(dp.tolist(), g.tolist(), 3)
+        assert np.array_equal(oracle.upscale(dp, g, 3), as_np(exp, np.int16))
+
+
+def test_upscale_linear_rows_and_bilateral_columns():
+    """Step8: odd rows are the mean of their neighbours; an odd column between
+    disparities further apart than T takes the side of closer gray."""
+    dp = np.array([[2, 10], [4, 10]], np.int16)
+    g = np.array([[0, 0, 200, 200], [0, 0, 0, 0], [0, 0, 200, 200], [0, 0, 0, 0]], np.uint8)
+    out = oracle.upscale(dp, g, 3)
+    # row 0: x=1 lies between 2 and 10 (> T), gray 0 is closer to the left
+    assert out[0].tolist() == [4, 4, 20, 20]
+    assert out[2].tolist() == [8, 8, 20, 20]
+    assert out[1].tolist() == [6, 6, 20, 20]
