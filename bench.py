@@ -1,0 +1,157 @@
+"""Throughput of the stereo path on one MI355X (one JSON line on stdout).
+
+Workload: one synthetic 1436x992 RGB pair with Dmax = 145 (718x496, D = 73
+at half resolution), the image size and disparity range the paper times
+(Table II, first row).  Inputs stay resident in device memory; a step is
+one full pass of the path (downscale through upscale) over the pair.
+
+Also reported: MDE/s (W * H * Dmax * fps / 1e6, the paper's Table III
+unit), p50/p99 single-frame latency, per-stage device times (Table II
+columns) from HIP events on the launch stream, the roofline of the fused
+cost/aggregation/WTA kernel, and the CPU oracle timed on this host on a
+bounded sample of the same workload.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+WORKLOAD = "paper_1436x992_d145"
+W, H, DMAX = 1436, 992, 145
+PAPER_FPS = 40.0  # Table II / abstract, GTX 780 Ti, Adirondack at this size
+# Peak integer VALU rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
+# Algorithmic integer operations per half-res evaluation (x, y, d), both
+# base images: the cost (abs-diff, xor, popcount, table add: 4, shared by the
+# two bases through Eq. 6) and, per base, row prefix add, CA_x difference,
+# column prefix add, CA difference and the WTA compare (5 x 2).
+OPS_PER_EVAL = 4 + 2 * 5
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--latency-frames", type=int, default=100)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    return ap.parse_args()
+
+
+def percentile(v, q):
+    v = sorted(v)
+    i = min(len(v) - 1, max(0, int(round(q / 100.0 * (len(v) - 1)))))
+    return v[i]
+
+
+def cpu_baseline(pair, seconds):
+    """The oracle as it stands, on this host's cores, for ~`seconds`."""
+    import oracle
+    oracle.lib()
+    frames, t0 = 0, time.perf_counter()
+    while True:
+        oracle.disparity(pair.left, pair.right, DMAX)
+        frames += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    fps = frames / el
+    return {"value": round(fps, 4), "unit": "frames/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"{frames} full {W}x{H} Dmax={DMAX} frames in {el:.1f} s",
+            "mde_per_s": round(W * H * DMAX * fps / 1e6, 2)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
+                          "(frames are independent, see the sharding notes)"}))
+        sys.exit(2)
+    import torch
+    import paper_2212_00488_amd as sm
+    from paper_2212_00488_amd.synth import workload_pairs
+
+    pair = workload_pairs(WORKLOAD)[0]
+    dev = torch.device("cuda:0")
+    left = torch.from_numpy(pair.left).to(dev)
+    right = torch.from_numpy(pair.right).to(dev)
+    out = torch.empty((H, W), dtype=torch.int16, device=dev)
+    ctx = sm.Stereo(0)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        ctx.disparity(left, right, DMAX, out=out)
+    torch.cuda.synchronize()
+
+    # throughput: K back-to-back frames
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(stream)
+    for _ in range(args.steps):
+        ctx.disparity(left, right, DMAX, out=out)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    ms_total = t0.elapsed_time(t1)
+    ms_step = ms_total / args.steps
+    fps = 1000.0 / ms_step
+
+    # per-stage device times from HIP events on the launch stream
+    tp = sm.default_params(flags=sm.F_STAGE_TIMING)
+    ctx.stage_times(reset=True)
+    for _ in range(args.steps):
+        ctx.disparity(left, right, DMAX, tp, out=out)
+    stages, ncalls = ctx.stage_times(reset=True)
+    stage_ms = {k: v / ncalls for k, v in stages.items()}
+
+    # single-frame latency: launch to completion, one frame in flight
+    lat = []
+    for _ in range(args.latency_frames):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        ctx.disparity(left, right, DMAX, out=out)
+        b.record(stream)
+        b.synchronize()
+        lat.append(a.elapsed_time(b))
+
+    X, Y, D = (W + 1) // 2, (H + 1) // 2, (DMAX + 1) // 2
+    evals = X * Y * D
+    t_match = stage_ms["cost_aggregate_wta"] / 1000.0
+    achieved = OPS_PER_EVAL * evals / t_match
+    res = {
+        "metric": "fps & MDE/s at 1436x992 D=145 vs plain; p50/p99 frame latency",
+        "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_step, 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": round(fps / PAPER_FPS, 2),
+        "baseline_note": "paper: 40 fps on a GTX 780 Ti (Adirondack, same size); context only",
+        "dtype": "int32", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "W": W, "H": H, "Dmax": DMAX, "pairs_per_step": 1,
+                   "half_res": [X, Y, D]},
+        "mde_per_s": round(W * H * DMAX * fps / 1e6, 1),
+        "latency_ms": {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)},
+        "stages_ms": {k: round(v, 5) for k, v in stage_ms.items()},
+        "roofline": {"kernel": "k_match", "bound": "alu", "achieved": round(achieved / 1e12, 3),
+                     "peak": round(PEAK_INT_OPS / 1e12, 3), "unit": "Tops/s",
+                     "frac": round(achieved / PEAK_INT_OPS, 4), "traffic": None,
+                     "ops_per_eval": OPS_PER_EVAL, "evals_per_launch": evals,
+                     "avg_launch_ms": round(stage_ms["cost_aggregate_wta"], 5)},
+    }
+    ctx.close()
+    if not args.no_cpu:
+        res["cpu_baseline"] = cpu_baseline(pair, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,9 @@
+"""MI355X-native stereo matching after Chang & Maruyama (arXiv 2212.00488).
+
+``binding`` holds the ctypes front end of the C interface (include/stereo.h);
+``synth`` the seeded synthetic stereo pairs; ``build`` the hipcc build.
+Importing the package loads nothing; the library is loaded on first use.
+"""
+
+from .binding import (F_KEEP_INTERMEDIATES, F_STAGE_TIMING, STAGES, Params,  # noqa: F401
+                      Stereo, StereoError, default_params, lib)

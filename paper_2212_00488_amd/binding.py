@@ -1,0 +1,199 @@
+"""ctypes binding of the C interface in include/stereo.h.
+
+Marshalling only: torch tensors provide device memory and the HIP stream,
+every step of the path runs in the library's kernels.  The library must be
+built (``__graft_entry__.build()``); nothing falls back to another
+implementation when it is missing.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .build import LIB
+
+OK, EINVAL, ENOMEM, EHIP, EUNIMPL = 0, -1, -2, -3, -4
+F_KEEP_INTERMEDIATES = 1
+F_STAGE_TIMING = 2
+STAGES = ("downscale", "census_arms", "cost_aggregate_wta", "chunk_min_crosscheck",
+          "median_fill", "upscale")
+
+# stereo_intermediate: id -> (dtype, trailing dims)
+INTERMEDIATES = {
+    "half_l": (1, np.uint8, ()), "half_r": (2, np.uint8, ()),
+    "census_l": (3, np.uint8, ()), "census_r": (4, np.uint8, ()),
+    "arms_l": (5, np.uint8, (4,)), "arms_r": (6, np.uint8, (4,)),
+    "cost_l_d": (7, np.uint16, ()), "cost_r_d": (8, np.uint16, ()),
+    "cax_l_d": (9, np.uint32, ()), "cax_r_d": (10, np.uint32, ()),
+    "ca_l_d": (11, np.uint32, ()), "ca_r_d": (12, np.uint32, ()),
+    "mincost_l": (13, np.uint32, ()), "mincost_r": (14, np.uint32, ()),
+    "disp_l": (15, np.int16, ()), "disp_r": (16, np.int16, ()),
+    "gcp": (17, np.uint8, ()), "median": (18, np.int16, ()), "filled": (19, np.int16, ()),
+}
+I_LUT = 20
+
+
+class Params(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("lambda_ad", ctypes.c_float),
+                ("lambda_mc", ctypes.c_float), ("cost_scale", ctypes.c_int32),
+                ("color_delta", ctypes.c_int32), ("arm_x", ctypes.c_int32),
+                ("arm_y", ctypes.c_int32), ("fill_T", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+class StereoError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"stereo error {code}: {msg}")
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            raise RuntimeError(f"{LIB} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB)
+        P, I, U = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+        L.stereo_default_params.argtypes = [ctypes.POINTER(Params)]
+        L.stereo_default_params.restype = None
+        L.stereo_create.argtypes = [ctypes.POINTER(P), I, U]
+        L.stereo_create.restype = I
+        L.stereo_destroy.argtypes = [P]
+        L.stereo_destroy.restype = None
+        L.stereo_last_error.argtypes = [P]
+        L.stereo_last_error.restype = ctypes.c_char_p
+        L.stereo_disparity.argtypes = [P, P, P, I, I, I, ctypes.POINTER(Params), P, P]
+        L.stereo_disparity.restype = I
+        L.stereo_disparity_batch.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), I, I, I, I,
+                                             ctypes.POINTER(Params), ctypes.POINTER(P), P]
+        L.stereo_disparity_batch.restype = I
+        L.stereo_get_intermediate.argtypes = [P, I, I, P, U, P]
+        L.stereo_get_intermediate.restype = I
+        L.stereo_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_double),
+                                         ctypes.POINTER(ctypes.c_int), I]
+        L.stereo_stage_times.restype = I
+        _lib = L
+    return _lib
+
+
+def default_params(**overrides) -> Params:
+    p = Params()
+    lib().stereo_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_image(t, name):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != torch.uint8 or t.dim() != 3 or t.shape[2] != 3 or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous uint8 [H][W][3] tensor")
+
+
+class Stereo:
+    """A library context on one HIP device."""
+
+    def __init__(self, device: int = 0, mem_cap: int = 0):
+        self.device = device
+        h = ctypes.c_void_p()
+        rc = lib().stereo_create(ctypes.byref(h), device, mem_cap)
+        if rc:
+            raise StereoError(rc, f"stereo_create(device={device}) failed")
+        self._h = h
+        self._last_shape = None
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().stereo_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self) -> str:
+        return lib().stereo_last_error(self._h).decode()
+
+    def _raise(self, rc):
+        if rc:
+            raise StereoError(rc, self.last_error())
+
+    def disparity(self, left, right, dmax: int, params: Params | None = None, out=None,
+                  stream=None):
+        """Full-resolution int16 disparity map of one pair of [H][W][3] uint8 images."""
+        import torch
+        _check_image(left, "left")
+        _check_image(right, "right")
+        H, W, _ = left.shape
+        if tuple(right.shape) != (H, W, 3):
+            raise ValueError("left and right shapes differ")
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.int16, device=left.device)
+        rc = lib().stereo_disparity(self._h, left.data_ptr(), right.data_ptr(), W, H, int(dmax),
+                                    ctypes.byref(params) if params is not None else None,
+                                    out.data_ptr(), _stream_handle(stream))
+        self._raise(rc)
+        self._last_shape = (W, H, dmax)
+        return out
+
+    def disparity_batch(self, lefts, rights, dmax: int, params: Params | None = None,
+                        outs=None, stream=None):
+        import torch
+        n = len(lefts)
+        if n != len(rights) or n < 1:
+            raise ValueError("need equally many left and right images")
+        for t in list(lefts) + list(rights):
+            _check_image(t, "image")
+        H, W, _ = lefts[0].shape
+        if outs is None:
+            outs = [torch.empty((H, W), dtype=torch.int16, device=lefts[0].device)
+                    for _ in range(n)]
+        arr = ctypes.c_void_p * n
+        rc = lib().stereo_disparity_batch(
+            self._h, arr(*[t.data_ptr() for t in lefts]), arr(*[t.data_ptr() for t in rights]),
+            n, W, H, int(dmax), ctypes.byref(params) if params is not None else None,
+            arr(*[t.data_ptr() for t in outs]), _stream_handle(stream))
+        self._raise(rc)
+        self._last_shape = (W, H, dmax)
+        return outs
+
+    def stage_times(self, reset: bool = True):
+        """(per-stage milliseconds summed over timed calls, number of calls)."""
+        ms = (ctypes.c_double * len(STAGES))()
+        n = ctypes.c_int()
+        self._raise(lib().stereo_stage_times(self._h, ms, ctypes.byref(n), int(reset)))
+        return dict(zip(STAGES, list(ms))), n.value
+
+    def intermediate(self, name: str, d: int = 0, stream=None) -> np.ndarray:
+        """A plane of the last call made with F_KEEP_INTERMEDIATES, as numpy."""
+        W, H, dmax = self._last_shape
+        if name == "lut":
+            buf = np.zeros(263, np.uint16)
+            rc = lib().stereo_get_intermediate(self._h, I_LUT, 0, buf.ctypes.data, buf.nbytes,
+                                               _stream_handle(stream))
+            self._raise(rc)
+            return buf
+        which, dt, tail = INTERMEDIATES[name]
+        buf = np.zeros(((H + 1) // 2, (W + 1) // 2) + tail, dt)
+        rc = lib().stereo_get_intermediate(self._h, which, int(d), buf.ctypes.data, buf.nbytes,
+                                           _stream_handle(stream))
+        self._raise(rc)
+        return buf

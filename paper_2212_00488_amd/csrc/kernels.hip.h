@@ -1,0 +1,463 @@
+// Device kernels of the stereo path (gfx950, wave64).
+//
+// Pipeline per pair (Sec. IV, Step1-8), all integer arithmetic:
+//   k_prep     RGB -> gray -> 3x3 mean at even coordinates    (Sec. III-A, Eq. 2)
+//   k_feat     mini-census + cross arms of both half images    (Sec. III-B, III-C)
+//   k_match    cost, x- and y-aggregation and WTA, fused: the  (Eq. 3-9)
+//              cost volume never leaves the chip
+//   k_wta_cc   combine the d-chunk minima, cross-check         (Eq. 9-10)
+//   k_refine   3x3 median and bilateral filling of non-GCPs    (Sec. III-E, Eq. 11)
+//   k_upscale  bilateral x / linear y upscale to full res      (Step8)
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stereo_dev {
+
+constexpr int kMaxPairs = 8;      // pairs per launch (batched entry point)
+constexpr int kTX = 64;           // k_match strip width = one wave
+constexpr int kWaves = 16;        // k_match workgroup = 16 waves
+constexpr int kThreads = kWaves * 64;
+constexpr int kKMax = 36;         // most output rows per k_match thread (band <= 576 rows)
+constexpr int kTab = 7 * 256;     // combined cost table [census distance][abs diff]
+constexpr int kLdsBytes = 163840; // LDS per workgroup on gfx950
+
+// Rows of the k_match LDS plane for a given number of 64-column sub-passes.
+__host__ __device__ constexpr int plane_rows(int nsub) {
+  return (kLdsBytes - kTab * 2 - kWaves * 64 * 4 - kWaves * nsub * 64 * 4) / 256 - 2;
+}
+
+struct PairPtrs {
+  const uint8_t* left[kMaxPairs];
+  const uint8_t* right[kMaxPairs];
+  int16_t* out[kMaxPairs];
+};
+
+__device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
+__device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+__device__ __forceinline__ int gray_of(const uint8_t* p) {
+  return (77 * p[0] + 150 * p[1] + 29 * p[2] + 128) >> 8;
+}
+
+// ---------------------------------------------------------------- k_prep
+// One thread per half-res pixel of one image: the rounded-half-up mean of
+// the 3x3 gray block centred on (2x, 2y), borders clamped.
+// grid: (ceil(X/64), ceil(Y/4), 2 * npair), block (64, 4).
+__global__ void __launch_bounds__(256) k_prep(PairPtrs pp, int W, int H, int X, int Y,
+                                              uint8_t* __restrict__ half) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  const int img = blockIdx.z;  // 2 * pair + (0 = left, 1 = right)
+  if (x >= X || y >= Y) return;
+  const int pair = img >> 1;
+  const uint8_t* rgb = (img & 1) ? pp.right[pair] : pp.left[pair];
+  int s = 0;
+#pragma unroll
+  for (int j = -1; j <= 1; ++j) {
+    const uint8_t* row = rgb + (size_t)clampi(2 * y + j, 0, H - 1) * W * 3;
+#pragma unroll
+    for (int i = -1; i <= 1; ++i) s += gray_of(row + clampi(2 * x + i, 0, W - 1) * 3);
+  }
+  half[(size_t)img * X * Y + (size_t)y * X + x] = (uint8_t)((s + 4) / 9);
+}
+
+// ---------------------------------------------------------------- k_feat
+// One thread per half-res pixel of one image.  Writes
+//   pk[img][y][x]   = gray | census << 8   (census: 6 neighbours in three rows,
+//                     bit k = [neighbour < centre], borders clamped)
+//   arms[img][y][x] = m | n << 8 | M << 16 | N << 24  (contiguous pixels with
+//                     |I - I(centre)| < delta, capped per side and at the border)
+__global__ void __launch_bounds__(256) k_feat(const uint8_t* __restrict__ half, int X, int Y,
+                                              int delta, int arm_x, int arm_y,
+                                              uint16_t* __restrict__ pk,
+                                              uint32_t* __restrict__ arms) {
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
+  const int img = blockIdx.z;
+  if (x >= X || y >= Y) return;
+  const uint8_t* h = half + (size_t)img * X * Y;
+  const int c = h[(size_t)y * X + x];
+  const int ym = clampi(y - 1, 0, Y - 1), yp = clampi(y + 1, 0, Y - 1);
+  const int xm1 = clampi(x - 1, 0, X - 1), xp1 = clampi(x + 1, 0, X - 1);
+  const int xm2 = clampi(x - 2, 0, X - 1), xp2 = clampi(x + 2, 0, X - 1);
+  int bits = 0;
+  bits |= (h[(size_t)ym * X + xm1] < c) << 0;
+  bits |= (h[(size_t)ym * X + xp1] < c) << 1;
+  bits |= (h[(size_t)y * X + xm2] < c) << 2;
+  bits |= (h[(size_t)y * X + xp2] < c) << 3;
+  bits |= (h[(size_t)yp * X + xm1] < c) << 4;
+  bits |= (h[(size_t)yp * X + xp1] < c) << 5;
+  const uint8_t* row = h + (size_t)y * X;
+  int m = 0, n = 0, M = 0, N = 0;
+  while (m < arm_x && x - m - 1 >= 0 && iabs(row[x - m - 1] - c) < delta) ++m;
+  while (n < arm_x && x + n + 1 < X && iabs(row[x + n + 1] - c) < delta) ++n;
+  while (M < arm_y && y - M - 1 >= 0 && iabs(h[(size_t)(y - M - 1) * X + x] - c) < delta) ++M;
+  while (N < arm_y && y + N + 1 < Y && iabs(h[(size_t)(y + N + 1) * X + x] - c) < delta) ++N;
+  const size_t o = (size_t)img * X * Y + (size_t)y * X + x;
+  pk[o] = (uint16_t)(c | (bits << 8));
+  arms[o] = (uint32_t)m | ((uint32_t)n << 8) | ((uint32_t)M << 16) | ((uint32_t)N << 24);
+}
+
+// ---------------------------------------------------------------- k_match
+// Inclusive prefix sum over the 64 lanes of a wave (DPP row shifts inside
+// rows of 16 lanes, then row broadcasts across rows).
+__device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x142, 0xa, 0xf, false);  // row_bcast:15
+  v += __builtin_amdgcn_update_dpp(0u, v, 0x143, 0xc, 0xf, false);  // row_bcast:31
+  return v;
+}
+
+// Keeps the compiler from moving LDS accesses of one wave across this point;
+// the LDS itself serves the accesses of a wave in issue order.
+#define WAVE_LDS_ORDER() __asm__ volatile("" ::: "memory")
+
+struct MatchArgs {
+  const uint16_t* pk;     // [2*npair][Y][X]  gray | census << 8
+  const uint32_t* arms;   // [2*npair][Y][X]
+  const uint16_t* tab;    // [7][256] combined cost table
+  uint32_t* keys;         // [npair][nchunk][2][Y][X]  (min CA) << 8 | argmin d
+  int X, Y, arm_x, arm_y, cmax;
+  int nbands, nchunk, dlo, dhi;
+  // debug planes (pair 0, the single disparity dlo; NULL in the fast path)
+  uint16_t* dbg_cost;
+  uint32_t* dbg_cax;
+  uint32_t* dbg_ca;
+  int dbg_base;
+};
+
+// One workgroup = one 64-column strip x one band of rows x one base image
+// x one chunk of disparities.  For each d of the chunk:
+//   row pass   : each wave takes rows of the band; C (Eq. 3-5, table lookup) over
+//                the strip plus arm_x+1 columns either side, inclusive wave scan,
+//                CA_x = P[x+n] - P[x-m-1] (Eq. 7) into the LDS plane;
+//   column pass: segmented prefix down each column of the plane, in place, then
+//                CA = Q[y+N] - Q[y-M-1] (Eq. 8) for the band's output rows and
+//                key = min(key, CA << 8 | d): the smallest d wins ties (Step5).
+// The right-based cost is evaluated as cost(R(x), L(x+d)), which is C^L(x+d)
+// of Eq. 6 term for term.  Sums wrap modulo 2^32; every difference taken is a
+// window sum below 2^24, hence exact.
+// KMAX (<= kKMax) bounds the output rows per thread: a band has at most
+// 16 * KMAX output rows.
+// grid: (nstrips, nbands * nchunk, 2 * npair), block 1024.
+template <int NSUB, int KMAX>
+__global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
+  constexpr int PR = plane_rows(NSUB);
+  __shared__ uint16_t s_tab[kTab];
+  __shared__ uint32_t s_row[kWaves][NSUB * 64];
+  __shared__ uint32_t s_seg[kWaves][64];
+  __shared__ uint32_t s_plane[(PR + 1) * 64];  // row 0 = zeros (band row -1)
+
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int X = a.X, Y = a.Y;
+  const int x0 = blockIdx.x * kTX;
+  const int band = blockIdx.y % a.nbands, chunk = blockIdx.y / a.nbands;
+  const int pair = blockIdx.z >> 1, base = blockIdx.z & 1;
+  const int ob = (Y + a.nbands - 1) / a.nbands;
+  const int y0 = band * ob, y1 = min(Y, y0 + ob);
+  const int ya = max(0, y0 - a.arm_y), yb = min(Y, y1 + a.arm_y);
+  const int nb = yb - ya, o0 = y0 - ya, o1 = y1 - ya;
+  const int span = a.dhi - a.dlo;
+  const int d0 = a.dlo + (chunk * span) / a.nchunk, d1 = a.dlo + ((chunk + 1) * span) / a.nchunk;
+  const int hx = a.arm_x + 1;          // first column of the row buffer is x0 - hx
+  const int sgn = base ? 1 : -1;       // other-image column is x + sgn * d
+  const size_t plane = (size_t)X * Y;
+  const uint16_t* pkb = a.pk + (size_t)(2 * pair + base) * plane;
+  const uint16_t* pko = a.pk + (size_t)(2 * pair + (base ^ 1)) * plane;
+  const uint32_t* armb = a.arms + (size_t)(2 * pair + base) * plane;
+  const bool dbg = a.dbg_cost != nullptr && pair == 0 && base == a.dbg_base;
+
+  for (int i = t; i < kTab; i += kThreads) s_tab[i] = a.tab[i];
+  if (t < 64) s_plane[t] = 0u;
+
+  const int c = lane, x = x0 + lane;
+  const int seg_len = (nb + kWaves - 1) / kWaves;
+  const int r0 = min(wave * seg_len, nb), r1 = min(r0 + seg_len, nb);
+
+  // Output rows of this thread: r = o0 + wave + 16 k.  marm[k / 2] packs the
+  // vertical arms (M, N) of two such rows, one byte each.  Rows outside the
+  // band or columns outside the image get M = N = 0; their keys are never
+  // stored.
+  static_assert(KMAX % 2 == 0, "KMAX must be even");
+  uint32_t key[KMAX], marm[KMAX / 2];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    key[k] = 0xffffffffu;
+    uint32_t mn = 0u;
+    const int r = o0 + wave + k * kWaves;
+    if (x < X && r < o1) mn = armb[(size_t)(ya + r) * X + x] >> 16;
+    if (k & 1) marm[k / 2] |= mn << 16;
+    else marm[k / 2] = mn;
+  }
+  // plane word of (band row o0 + wave, column c); plane row = band row + 1
+  const int fin_base = (o0 + wave + 1) * 64 + c;
+  __syncthreads();
+
+  for (int d = d0; d < d1; ++d) {
+    // ---- row pass
+    for (int r = wave; r < nb; r += kWaves) {
+      const int y = ya + r;
+      const uint16_t* rb = pkb + (size_t)y * X;
+      const uint16_t* ro = pko + (size_t)y * X;
+      uint32_t carry = 0;
+#pragma unroll
+      for (int j = 0; j < NSUB; ++j) {
+        const int xc = x0 - hx + j * 64 + lane;
+        uint32_t cst = 0;
+        if (xc >= 0 && xc < X) {
+          const int xo = xc + sgn * d;
+          if (xo < 0 || xo >= X) {
+            cst = (uint32_t)a.cmax;
+          } else {
+            const uint32_t b = rb[xc], o = ro[xo];
+            const int ad = iabs((int)(b & 255u) - (int)(o & 255u));
+            const int hd = __builtin_popcount((b ^ o) >> 8);
+            cst = s_tab[hd * 256 + ad];
+          }
+          if (dbg && d == a.dlo && xc >= x0 && xc < x0 + kTX && y >= y0 && y < y1)
+            a.dbg_cost[(size_t)y * X + xc] = (uint16_t)cst;
+        }
+        const uint32_t p = wave_scan_incl(cst) + carry;
+        carry = __builtin_amdgcn_readlane(p, 63);
+        s_row[wave][j * 64 + lane] = p;
+      }
+      WAVE_LDS_ORDER();
+      uint32_t cax = 0;
+      if (x < X) {
+        const uint32_t am = armb[(size_t)y * X + x];
+        const int m = am & 255u, n = (am >> 8) & 255u;
+        cax = s_row[wave][lane + hx + n] - s_row[wave][lane + hx - m - 1];
+        if (dbg && d == a.dlo && y >= y0 && y < y1) a.dbg_cax[(size_t)y * X + x] = cax;
+      }
+      s_plane[(r + 1) * 64 + lane] = cax;
+      WAVE_LDS_ORDER();
+    }
+    __syncthreads();
+    // ---- column pass: segment sums, segment offsets, prefix in place
+    uint32_t acc = 0;
+    for (int r = r0; r < r1; ++r) acc += s_plane[(r + 1) * 64 + c];
+    s_seg[wave][c] = acc;
+    __syncthreads();
+    uint32_t off = 0;
+    for (int s = 0; s < wave; ++s) off += s_seg[s][c];
+    for (int r = r0; r < r1; ++r) {
+      off += s_plane[(r + 1) * 64 + c];
+      s_plane[(r + 1) * 64 + c] = off;
+    }
+    __syncthreads();
+    // ---- vertical window and WTA for this wave's output rows
+#pragma unroll
+    for (int j = 0; j < KMAX / 2; ++j) {
+      uint32_t mj = marm[j];
+      __asm__ volatile("" : "+v"(mj));  // keep the address math inside the d loop
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = 2 * j + h;
+        const int M = (mj >> (16 * h)) & 255u, N = (mj >> (16 * h + 8)) & 255u;
+        // per-lane part first; the per-row part k * 1024 words becomes the
+        // immediate offset of the LDS read
+        const int lo = fin_base - (M + 1) * 64, hi = fin_base + N * 64;
+        const uint32_t ca = s_plane[hi + k * kWaves * 64] - s_plane[lo + k * kWaves * 64];
+        const uint32_t kv = (ca << 8) | (uint32_t)d;
+        key[k] = kv < key[k] ? kv : key[k];
+      }
+    }
+    __syncthreads();
+  }
+
+  int nout = o1 - o0 - wave;  // output rows left for this wave, from row k = 0
+  __asm__ volatile("" : "+v"(nout));  // recompute the row tests here
+  if (x < X) {
+    uint32_t* out = a.keys + ((size_t)(pair * a.nchunk + chunk) * 2 + base) * plane;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int r = o0 + wave + k * kWaves;
+      if (k * kWaves < nout) {
+        out[(size_t)(ya + r) * X + x] = key[k];
+        // a debug run covers the single disparity dlo, so the key holds CA
+        if (dbg) a.dbg_ca[(size_t)(ya + r) * X + x] = key[k] >> 8;
+      }
+    }
+  }
+}
+
+// -------------------------------------------------------------- k_wta_cc
+// One workgroup per half-res row: min over the d-chunk keys gives D^L, D^R
+// (and the minimum aggregates when mincost != NULL); then the cross-check
+// GCP = [x - k >= 0 and D^R(x - k) = k], k = D^L(x)  (Eq. 10).
+// grid: (Y, npair), block 256.
+__global__ void __launch_bounds__(256) k_wta_cc(const uint32_t* __restrict__ keys, int nchunk,
+                                                int X, int Y, int16_t* __restrict__ disp,
+                                                uint32_t* __restrict__ mincost,
+                                                uint8_t* __restrict__ gcp) {
+  __shared__ int16_t s_dr[4096];
+  __shared__ int16_t s_dl[4096];
+  const int y = blockIdx.x, pair = blockIdx.y;
+  const size_t plane = (size_t)X * Y;
+  const uint32_t* kp = keys + (size_t)pair * nchunk * 2 * plane;
+  for (int x = threadIdx.x; x < X; x += 256) {
+    uint32_t kl = 0xffffffffu, kr = 0xffffffffu;
+    for (int c = 0; c < nchunk; ++c) {
+      const uint32_t vl = kp[((size_t)c * 2 + 0) * plane + (size_t)y * X + x];
+      const uint32_t vr = kp[((size_t)c * 2 + 1) * plane + (size_t)y * X + x];
+      kl = vl < kl ? vl : kl;
+      kr = vr < kr ? vr : kr;
+    }
+    const size_t o = (size_t)y * X + x;
+    s_dl[x] = (int16_t)(kl & 255u);
+    s_dr[x] = (int16_t)(kr & 255u);
+    disp[(size_t)(2 * pair) * plane + o] = (int16_t)(kl & 255u);
+    disp[(size_t)(2 * pair + 1) * plane + o] = (int16_t)(kr & 255u);
+    if (mincost) {
+      mincost[(size_t)(2 * pair) * plane + o] = kl >> 8;
+      mincost[(size_t)(2 * pair + 1) * plane + o] = kr >> 8;
+    }
+  }
+  __syncthreads();
+  for (int x = threadIdx.x; x < X; x += 256) {
+    const int k = s_dl[x];
+    gcp[(size_t)pair * plane + (size_t)y * X + x] = (uint8_t)(x - k >= 0 && s_dr[x - k] == k);
+  }
+}
+
+// -------------------------------------------------------------- k_refine
+// One workgroup per half-res row: M = 3x3 median of D^L (borders clamped);
+// GCPs keep M; a non-GCP takes the nearest GCPs left (x-i) and right (x+j):
+// linear interpolation from M(x-i) toward M(x+j), rounded half up, when they
+// differ by at most T, else the side of strictly closer brightness (the right
+// one on a tie) (Sec. III-E).  One side only: copy it; none: 0.
+// grid: (Y, npair), block 256.
+__device__ __forceinline__ int floor_div_pos(int n, int d) {  // d > 0
+  return n >= 0 ? n / d : -((-n + d - 1) / d);
+}
+
+__device__ __forceinline__ int median9(int* v) {
+  // 19-comparator median-of-9 selection network (Paeth, Graphics Gems;
+  // exhaustively checked on all 0/1 inputs by the test suite's CPU twin)
+#define CS(i, j) { int lo = min(v[i], v[j]); int hi = max(v[i], v[j]); v[i] = lo; v[j] = hi; }
+  CS(1, 2) CS(4, 5) CS(7, 8) CS(0, 1) CS(3, 4) CS(6, 7) CS(1, 2) CS(4, 5) CS(7, 8)
+  CS(0, 3) CS(5, 8) CS(4, 7) CS(3, 6) CS(1, 4) CS(2, 5) CS(4, 7) CS(4, 2) CS(6, 4)
+  CS(4, 2)
+#undef CS
+  return v[4];
+}
+
+__global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp,
+                                                const uint8_t* __restrict__ gcp,
+                                                const uint16_t* __restrict__ pk, int X, int Y,
+                                                int T, int16_t* __restrict__ med_out,
+                                                int16_t* __restrict__ filled) {
+  __shared__ int16_t s_med[4096];
+  __shared__ uint8_t s_g[4096];
+  __shared__ uint8_t s_h[4096];
+  __shared__ int16_t s_xl[4096];
+  __shared__ int s_lastg[256];
+  __shared__ int s_firstg[256];
+  const int y = blockIdx.x, pair = blockIdx.y, t = threadIdx.x;
+  const size_t plane = (size_t)X * Y;
+  const int16_t* dl = disp + (size_t)(2 * pair) * plane;
+  const int ym = max(y - 1, 0), yp = min(y + 1, Y - 1);
+  for (int x = t; x < X; x += 256) {
+    const int xm = max(x - 1, 0), xp = min(x + 1, X - 1);
+    int v[9] = {dl[(size_t)ym * X + xm], dl[(size_t)ym * X + x], dl[(size_t)ym * X + xp],
+                dl[(size_t)y * X + xm],  dl[(size_t)y * X + x],  dl[(size_t)y * X + xp],
+                dl[(size_t)yp * X + xm], dl[(size_t)yp * X + x], dl[(size_t)yp * X + xp]};
+    const int m = median9(v);
+    s_med[x] = (int16_t)m;
+    if (med_out) med_out[(size_t)pair * plane + (size_t)y * X + x] = (int16_t)m;
+    s_g[x] = gcp[(size_t)pair * plane + (size_t)y * X + x];
+    s_h[x] = (uint8_t)(pk[(size_t)(2 * pair) * plane + (size_t)y * X + x] & 255u);
+  }
+  __syncthreads();
+  // nearest GCP to the left / right: contiguous segments per thread + scans
+  const int cpt = (X + 255) / 256;
+  const int sx0 = min(t * cpt, X), sx1 = min(sx0 + cpt, X);
+  int lastg = -1, firstg = X;
+  for (int x = sx0; x < sx1; ++x)
+    if (s_g[x]) { lastg = x; if (firstg == X) firstg = x; }
+  s_lastg[t] = lastg;
+  s_firstg[t] = firstg;
+  __syncthreads();
+  for (int st = 1; st < 256; st <<= 1) {  // inclusive max-scan / reverse min-scan
+    const int a = t >= st ? s_lastg[t - st] : -1;
+    const int b = t + st < 256 ? s_firstg[t + st] : X;
+    __syncthreads();
+    s_lastg[t] = max(s_lastg[t], a);
+    s_firstg[t] = min(s_firstg[t], b);
+    __syncthreads();
+  }
+  int prev = t > 0 ? s_lastg[t - 1] : -1;
+  for (int x = sx0; x < sx1; ++x) {
+    s_xl[x] = (int16_t)prev;
+    if (s_g[x]) prev = x;
+  }
+  int next = t < 255 ? s_firstg[t + 1] : X;
+  int16_t* fo = filled + (size_t)pair * plane + (size_t)y * X;
+  for (int x = sx1 - 1; x >= sx0; --x) {
+    int v;
+    if (s_g[x]) {
+      v = s_med[x];
+      next = x;
+    } else {
+      const int xl = s_xl[x], xr = next;
+      if (xl >= 0 && xr < X) {
+        const int i = x - xl, j = xr - x, dla = s_med[xl], drb = s_med[xr];
+        if (iabs(dla - drb) <= T) {
+          v = dla + floor_div_pos(2 * i * (drb - dla) + (i + j), 2 * (i + j));
+        } else {
+          const int ch = s_h[x];
+          v = iabs(s_h[xl] - ch) < iabs(s_h[xr] - ch) ? dla : drb;
+        }
+      } else if (xl >= 0) {
+        v = s_med[xl];
+      } else if (xr < X) {
+        v = s_med[xr];
+      } else {
+        v = 0;
+      }
+    }
+    fo[x] = (int16_t)v;
+  }
+}
+
+// ------------------------------------------------------------- k_upscale
+// One thread per full-res output pixel (Step8).  Along x: even columns take
+// 2 D+(x); an odd column between D+(x) and D+(x+1) takes their sum (the
+// doubled midpoint) when they differ by at most T, else the doubled value of
+// the side whose full-res gray is strictly closer (the right one on a tie);
+// a last odd column copies.  Along y: odd rows are the rounded-up mean of
+// the two neighbouring upscaled rows; a last odd row copies.
+// grid: (ceil(W/64), ceil(H/4), npair), block (64, 4).
+__device__ __forceinline__ int up_x(const int16_t* frow, const uint8_t* rgb_row, int xo, int X,
+                                    int T) {
+  const int x = xo >> 1;
+  const int dlv = frow[x];
+  if ((xo & 1) == 0 || x + 1 >= X) return 2 * dlv;
+  const int drv = frow[x + 1];
+  if (iabs(dlv - drv) <= T) return dlv + drv;
+  const int g0 = gray_of(rgb_row + (xo - 1) * 3), g1 = gray_of(rgb_row + xo * 3),
+            g2 = gray_of(rgb_row + (xo + 1) * 3);
+  return iabs(g0 - g1) < iabs(g2 - g1) ? 2 * dlv : 2 * drv;
+}
+
+__global__ void __launch_bounds__(256) k_upscale(PairPtrs pp, const int16_t* __restrict__ filled,
+                                                 int W, int H, int X, int Y, int T) {
+  const int xo = blockIdx.x * 64 + threadIdx.x;
+  const int yo = blockIdx.y * 4 + threadIdx.y;
+  const int pair = blockIdx.z;
+  if (xo >= W || yo >= H) return;
+  const int16_t* f = filled + (size_t)pair * X * Y;
+  const uint8_t* rgb = pp.left[pair];
+  const int y = yo >> 1;
+  int v = up_x(f + (size_t)y * X, rgb + (size_t)(2 * y) * W * 3, xo, X, T);
+  if ((yo & 1) && y + 1 < Y) {
+    const int v2 = up_x(f + (size_t)(y + 1) * X, rgb + (size_t)(2 * y + 2) * W * 3, xo, X, T);
+    v = (v + v2 + 1) >> 1;
+  }
+  pp.out[pair][(size_t)yo * W + xo] = (int16_t)v;
+}
+
+}  // namespace stereo_dev

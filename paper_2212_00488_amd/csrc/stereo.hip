@@ -1,0 +1,546 @@
+// Host side of the stereo library: context, per-shape plans, launches and
+// the C interface declared in include/stereo.h.
+#include "stereo.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.hip.h"
+
+using namespace stereo_dev;
+
+namespace {
+
+// Cost tables of Eq. 4 and Eq. 5 in fixed point: S(1 - exp(-t)) rounded half
+// up, with t = (a / 255) / lambda_AD for brightness difference a and
+// t = h / lambda_MC for census Hamming distance h.
+void build_tables(const stereo_params& p, uint16_t ad[256], uint16_t mc[7]) {
+  const double S = p.cost_scale, lad = p.lambda_ad, lmc = p.lambda_mc;
+  for (int a = 0; a < 256; ++a) ad[a] = (uint16_t)std::floor(S * (1.0 - std::exp(-(a / 255.0) / lad)) + 0.5);
+  for (int h = 0; h < 7; ++h) mc[h] = (uint16_t)std::floor(S * (1.0 - std::exp(-h / lmc)) + 0.5);
+}
+
+struct Plan {
+  int W = 0, H = 0, Dmax = 0, X = 0, Y = 0, D = 0, npair = 0;
+  stereo_params p{};
+  uint16_t lut_ad[256]{}, lut_mc[7]{};
+  int cmax = 0;
+  int nsub = 2, kmax = 8, nstrips = 0, nbands = 0, nchunk = 0;
+  size_t bytes = 0;
+  // device memory, one block carved into planes
+  void* block = nullptr;
+  uint8_t* half = nullptr;    // [2*npair][Y][X]
+  uint16_t* pk = nullptr;     // [2*npair][Y][X]
+  uint32_t* arms = nullptr;   // [2*npair][Y][X]
+  uint16_t* tab = nullptr;    // [7][256]
+  uint32_t* keys = nullptr;   // [npair][nchunk][2][Y][X]
+  int16_t* disp = nullptr;    // [2*npair][Y][X]
+  uint32_t* mincost = nullptr;// [2*npair][Y][X]
+  uint8_t* gcp = nullptr;     // [npair][Y][X]
+  int16_t* med = nullptr;     // [npair][Y][X]
+  int16_t* filled = nullptr;  // [npair][Y][X]
+  // debug planes, allocated on demand
+  void* dbg_block = nullptr;
+  uint16_t* dbg_cost = nullptr;
+  uint32_t* dbg_cax = nullptr;
+  uint32_t* dbg_ca = nullptr;
+  uint64_t last_use = 0;
+};
+
+bool same_params(const stereo_params& a, const stereo_params& b) {
+  return a.lambda_ad == b.lambda_ad && a.lambda_mc == b.lambda_mc && a.cost_scale == b.cost_scale &&
+         a.color_delta == b.color_delta && a.arm_x == b.arm_x && a.arm_y == b.arm_y &&
+         a.fill_T == b.fill_T;
+}
+
+}  // namespace
+
+struct stereo_ctx {
+  int device = 0;
+  // stage timing: one set of STEREO_NUM_STAGES + 1 events per timed call
+  std::vector<hipEvent_t> events;
+  int timed_calls = 0;
+  int num_cu = 256;
+  size_t mem_cap = 0, used = 0;
+  std::vector<Plan*> plans;
+  std::string err;
+  Plan* last = nullptr;  // plan of the last call that kept its intermediates
+  uint64_t tick = 0;
+};
+
+namespace {
+
+int fail(stereo_ctx* c, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return code;
+}
+
+#define HIP_TRY(ctx, call)                                                              \
+  do {                                                                                  \
+    hipError_t e_ = (call);                                                             \
+    if (e_ != hipSuccess) return fail(ctx, STEREO_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+int check_params(stereo_ctx* c, const stereo_params& p) {
+  if (p.size != sizeof(stereo_params))
+    return fail(c, STEREO_EINVAL, "params.size %u != %zu", p.size, sizeof(stereo_params));
+  if (!(p.lambda_ad > 0.f) || !std::isfinite(p.lambda_ad) || !(p.lambda_mc > 0.f) ||
+      !std::isfinite(p.lambda_mc))
+    return fail(c, STEREO_EINVAL, "lambda_ad and lambda_mc must be finite and > 0");
+  if (p.cost_scale < 1 || p.cost_scale > 1024)
+    return fail(c, STEREO_EINVAL, "cost_scale %d outside 1..1024", p.cost_scale);
+  if (p.color_delta < 0 || p.color_delta > 256)
+    return fail(c, STEREO_EINVAL, "color_delta %d outside 0..256", p.color_delta);
+  if (p.arm_x < 0 || p.arm_x > 127 || p.arm_y < 0 || p.arm_y > 127)
+    return fail(c, STEREO_EINVAL, "arm caps must be in 0..127");
+  if (p.fill_T < 0 || p.fill_T > 1023) return fail(c, STEREO_EINVAL, "fill_T outside 0..1023");
+  uint16_t ad[256], mc[7];
+  build_tables(p, ad, mc);
+  const double cmax = (double)ad[255] + mc[6];
+  const double bound = (2.0 * p.arm_x + 1) * (2.0 * p.arm_y + 1) * cmax;
+  if (bound >= 16777216.0)
+    return fail(c, STEREO_EINVAL, "(2 arm_x + 1)(2 arm_y + 1) C_max = %.0f must be < 2^24", bound);
+  return 0;
+}
+
+void free_plan(Plan* pl) {
+  if (!pl) return;
+  if (pl->block) (void)hipFree(pl->block);
+  if (pl->dbg_block) (void)hipFree(pl->dbg_block);
+  delete pl;
+}
+
+template <class T>
+T* carve(char*& cur, size_t count) {
+  T* p = reinterpret_cast<T*>(cur);
+  cur += (count * sizeof(T) + 255) & ~size_t(255);
+  return p;
+}
+
+// Launch geometry: bands keep the k_match LDS plane and the per-thread key
+// registers within bounds; d-chunks raise the workgroup count to fill the CUs.
+void plan_geometry(Plan& pl, int num_cu) {
+  pl.nsub = (65 + 2 * pl.p.arm_x + 63) / 64;
+  if (pl.nsub < 2) pl.nsub = 2;
+  const int pr = plane_rows(pl.nsub);
+  // Output rows of a band are spread over the 16 waves, KMAX per thread
+  // (template steps 8..36).  The finalize of a band reads plane rows up to
+  // o0 + 16 KMAX (padding rows included, o0 <= arm_y is the top halo), and
+  // the band itself must fit the plane.
+  auto kstep = [](int rows_per_thread) {
+    for (int s : {8, 16, 24, 32, kKMax})
+      if (rows_per_thread <= s) return s;
+    return -1;
+  };
+  int nb = 1, km = 8;
+  for (;; ++nb) {
+    const int ob = (pl.Y + nb - 1) / nb;
+    km = kstep((ob + kWaves - 1) / kWaves);
+    if (km < 0) continue;
+    const int rows = nb == 1 ? pl.Y : ob + 2 * pl.p.arm_y;
+    const int o0max = nb == 1 ? 0 : pl.p.arm_y;
+    if (rows <= pr && o0max + kWaves * km <= pr) break;
+  }
+  pl.kmax = km;
+  pl.nbands = nb;
+  pl.nstrips = (pl.X + kTX - 1) / kTX;
+  const int per_chunk = pl.nstrips * pl.nbands * 2 * pl.npair;
+  // one k_match workgroup fits a CU at a time (LDS): split d into as many
+  // chunks as one round of CUs holds, at most D; each extra chunk costs one
+  // more key plane of traffic
+  pl.nchunk = std::max(1, std::min(pl.D, num_cu / per_chunk));
+}
+
+int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int npair,
+              Plan** out) {
+  Plan* pl = new Plan();
+  pl->W = W; pl->H = H; pl->Dmax = Dmax; pl->npair = npair;
+  pl->X = (W + 1) / 2; pl->Y = (H + 1) / 2; pl->D = (Dmax + 1) / 2;
+  pl->p = p;
+  build_tables(p, pl->lut_ad, pl->lut_mc);
+  pl->cmax = pl->lut_ad[255] + pl->lut_mc[6];
+  plan_geometry(*pl, c->num_cu);
+  const size_t n = (size_t)pl->X * pl->Y;
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  size_t bytes = al(2 * npair * n) + al(2 * npair * n * 2) + al(2 * npair * n * 4) + al(kTab * 2) +
+                 al((size_t)npair * pl->nchunk * 2 * n * 4) + al(2 * npair * n * 2) +
+                 al(2 * npair * n * 4) + al(npair * n) + al(npair * n * 2) + al(npair * n * 2);
+  if (c->mem_cap && c->used + bytes > c->mem_cap) {
+    delete pl;
+    return fail(c, STEREO_ENOMEM, "plan needs %zu bytes, cap %zu, in use %zu", bytes, c->mem_cap,
+                c->used);
+  }
+  hipError_t e = hipMalloc(&pl->block, bytes);
+  if (e != hipSuccess) {
+    delete pl;
+    (void)hipGetLastError();
+    return fail(c, STEREO_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+  }
+  pl->bytes = bytes;
+  char* cur = static_cast<char*>(pl->block);
+  pl->half = carve<uint8_t>(cur, 2 * npair * n);
+  pl->pk = carve<uint16_t>(cur, 2 * npair * n);
+  pl->arms = carve<uint32_t>(cur, 2 * npair * n);
+  pl->tab = carve<uint16_t>(cur, kTab);
+  pl->keys = carve<uint32_t>(cur, (size_t)npair * pl->nchunk * 2 * n);
+  pl->disp = carve<int16_t>(cur, 2 * npair * n);
+  pl->mincost = carve<uint32_t>(cur, 2 * npair * n);
+  pl->gcp = carve<uint8_t>(cur, npair * n);
+  pl->med = carve<int16_t>(cur, npair * n);
+  pl->filled = carve<int16_t>(cur, npair * n);
+  uint16_t tab[kTab];
+  for (int h = 0; h < 7; ++h)
+    for (int a = 0; a < 256; ++a) tab[h * 256 + a] = (uint16_t)(pl->lut_ad[a] + pl->lut_mc[h]);
+  e = hipMemcpy(pl->tab, tab, sizeof tab, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    free_plan(pl);
+    return fail(c, STEREO_EHIP, "hipMemcpy(tab): %s", hipGetErrorString(e));
+  }
+  c->used += bytes;
+  *out = pl;
+  return 0;
+}
+
+int get_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int npair, Plan** out) {
+  for (Plan* pl : c->plans)
+    if (pl->W == W && pl->H == H && pl->Dmax == Dmax && pl->npair >= npair && same_params(pl->p, p)) {
+      pl->last_use = ++c->tick;
+      *out = pl;
+      return 0;
+    }
+  Plan* pl = nullptr;
+  int rc = make_plan(c, W, H, Dmax, p, npair, &pl);
+  if (rc == STEREO_ENOMEM && !c->plans.empty()) {
+    // evict least recently used plans that are not the kept one, then retry
+    std::sort(c->plans.begin(), c->plans.end(),
+              [](Plan* a, Plan* b) { return a->last_use < b->last_use; });
+    for (size_t i = 0; i < c->plans.size() && rc == STEREO_ENOMEM;) {
+      if (c->plans[i] == c->last) { ++i; continue; }
+      (void)hipDeviceSynchronize();
+      c->used -= c->plans[i]->bytes;
+      free_plan(c->plans[i]);
+      c->plans.erase(c->plans.begin() + i);
+      rc = make_plan(c, W, H, Dmax, p, npair, &pl);
+    }
+  }
+  if (rc) return rc;
+  pl->last_use = ++c->tick;
+  c->plans.push_back(pl);
+  *out = pl;
+  return 0;
+}
+
+MatchArgs match_args(const Plan& pl, int dlo, int dhi, int nchunk) {
+  MatchArgs a{};
+  a.pk = pl.pk; a.arms = pl.arms; a.tab = pl.tab; a.keys = pl.keys;
+  a.X = pl.X; a.Y = pl.Y; a.arm_x = pl.p.arm_x; a.arm_y = pl.p.arm_y; a.cmax = pl.cmax;
+  a.nbands = pl.nbands; a.nchunk = nchunk; a.dlo = dlo; a.dhi = dhi;
+  return a;
+}
+
+template <int NSUB>
+void launch_match_k(const Plan& pl, const MatchArgs& a, dim3 grid, hipStream_t s) {
+  switch (pl.kmax) {
+    case 8: hipLaunchKernelGGL((k_match<NSUB, 8>), grid, dim3(kThreads), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_match<NSUB, 16>), grid, dim3(kThreads), 0, s, a); break;
+    case 24: hipLaunchKernelGGL((k_match<NSUB, 24>), grid, dim3(kThreads), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_match<NSUB, 32>), grid, dim3(kThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_match<NSUB, kKMax>), grid, dim3(kThreads), 0, s, a); break;
+  }
+}
+
+void launch_match(const Plan& pl, const MatchArgs& a, int npair, hipStream_t s) {
+  dim3 grid(pl.nstrips, pl.nbands * a.nchunk, 2 * npair);
+  switch (pl.nsub) {
+    case 2: launch_match_k<2>(pl, a, grid, s); break;
+    case 3: launch_match_k<3>(pl, a, grid, s); break;
+    case 4: launch_match_k<4>(pl, a, grid, s); break;
+    default: launch_match_k<5>(pl, a, grid, s); break;
+  }
+}
+
+// Events of the next timed call (created on first use, reused after reset).
+int timing_events(stereo_ctx* c, hipEvent_t** ev) {
+  const size_t per = STEREO_NUM_STAGES + 1, need = (size_t)(c->timed_calls + 1) * per;
+  while (c->events.size() < need) {
+    hipEvent_t e;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->events.push_back(e);
+  }
+  *ev = &c->events[(size_t)c->timed_calls * per];
+  return 0;
+}
+
+// The whole path for npair pairs already checked against the plan.
+int run(stereo_ctx* c, Plan& pl, const PairPtrs& pp, int npair, bool keep, bool timed,
+        hipStream_t s) {
+  const int X = pl.X, Y = pl.Y;
+  hipEvent_t* ev = nullptr;
+  if (timed) {
+    int rc = timing_events(c, &ev);
+    if (rc) return rc;
+  }
+  auto mark = [&](int i) { if (ev) (void)hipEventRecord(ev[i], s); };
+  dim3 b2(64, 4);
+  mark(0);
+  hipLaunchKernelGGL(k_prep, dim3((X + 63) / 64, (Y + 3) / 4, 2 * npair), b2, 0, s, pp, pl.W,
+                     pl.H, X, Y, pl.half);
+  mark(1);
+  hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + 3) / 4, 2 * npair), b2, 0, s, pl.half, X, Y,
+                     pl.p.color_delta, pl.p.arm_x, pl.p.arm_y, pl.pk, pl.arms);
+  mark(2);
+  launch_match(pl, match_args(pl, 0, pl.D, pl.nchunk), npair, s);
+  mark(3);
+  hipLaunchKernelGGL(k_wta_cc, dim3(Y, npair), dim3(256), 0, s, pl.keys, pl.nchunk, X, Y, pl.disp,
+                     keep ? pl.mincost : nullptr, pl.gcp);
+  mark(4);
+  hipLaunchKernelGGL(k_refine, dim3(Y, npair), dim3(256), 0, s, pl.disp, pl.gcp, pl.pk, X, Y,
+                     pl.p.fill_T, keep ? pl.med : nullptr, pl.filled);
+  mark(5);
+  hipLaunchKernelGGL(k_upscale, dim3((pl.W + 63) / 64, (pl.H + 3) / 4, npair), b2, 0, s, pp,
+                     pl.filled, pl.W, pl.H, X, Y, pl.p.fill_T);
+  mark(6);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, STEREO_EHIP, "kernel launch: %s", hipGetErrorString(e));
+  if (timed) ++c->timed_calls;
+  return 0;
+}
+
+int common_checks(stereo_ctx* c, int W, int H, int Dmax, const stereo_params* params,
+                  stereo_params* p) {
+  if (W < 2 || H < 2 || W > STEREO_MAX_SIDE || H > STEREO_MAX_SIDE)
+    return fail(c, STEREO_EINVAL, "image size %dx%d outside 2..%d", W, H, STEREO_MAX_SIDE);
+  if (Dmax < 1 || Dmax > W || Dmax > STEREO_MAX_DMAX)
+    return fail(c, STEREO_EINVAL, "Dmax %d outside 1..min(W=%d, %d)", Dmax, W, STEREO_MAX_DMAX);
+  if (params) {
+    if (params->size != sizeof(stereo_params))
+      return fail(c, STEREO_EINVAL, "params.size %u != %zu", params->size, sizeof(stereo_params));
+    *p = *params;
+  } else {
+    stereo_default_params(p);
+  }
+  return check_params(c, *p);
+}
+
+}  // namespace
+
+extern "C" {
+
+void stereo_default_params(stereo_params* p) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->size = sizeof(stereo_params);
+  p->lambda_ad = 0.3f;
+  p->lambda_mc = 2.3f;
+  p->cost_scale = 1024;
+  p->color_delta = 13;
+  p->arm_x = 21;
+  p->arm_y = 31;
+  p->fill_T = 3;
+  p->flags = 0;
+}
+
+int stereo_create(stereo_ctx** out, int device, size_t mem_cap) {
+  if (!out) return STEREO_EINVAL;
+  *out = nullptr;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || device < 0 || device >= n) {
+    (void)hipGetLastError();
+    return STEREO_EINVAL;
+  }
+  if (hipSetDevice(device) != hipSuccess) return STEREO_EHIP;
+  stereo_ctx* c = new stereo_ctx();
+  c->device = device;
+  c->mem_cap = mem_cap;
+  int cu = 0;
+  if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
+      cu > 0)
+    c->num_cu = cu;
+  *out = c;
+  return 0;
+}
+
+void stereo_destroy(stereo_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
+  for (Plan* pl : c->plans) free_plan(pl);
+  delete c;
+}
+
+const char* stereo_last_error(const stereo_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int stereo_disparity_batch(stereo_ctx* c, const uint8_t* const* left, const uint8_t* const* right,
+                           int n, int W, int H, int Dmax, const stereo_params* params,
+                           int16_t* const* out_disp, hipStream_t stream) {
+  if (!c) return STEREO_EINVAL;
+  c->err.clear();
+  if (!left || !right || !out_disp || n < 1) return fail(c, STEREO_EINVAL, "null pointer or n < 1");
+  for (int i = 0; i < n; ++i)
+    if (!left[i] || !right[i] || !out_disp[i]) return fail(c, STEREO_EINVAL, "null image pointer %d", i);
+  stereo_params p;
+  int rc = common_checks(c, W, H, Dmax, params, &p);
+  if (rc) return rc;
+  HIP_TRY(c, hipSetDevice(c->device));
+  const bool keep = (p.flags & STEREO_F_KEEP_INTERMEDIATES) != 0;
+  const int per = std::min(n, kMaxPairs);
+  Plan* pl = nullptr;
+  rc = get_plan(c, W, H, Dmax, p, per, &pl);
+  if (rc) return rc;
+  for (int i0 = 0; i0 < n; i0 += kMaxPairs) {
+    const int m = std::min(kMaxPairs, n - i0);
+    PairPtrs pp{};
+    for (int i = 0; i < m; ++i) {
+      pp.left[i] = left[i0 + i];
+      pp.right[i] = right[i0 + i];
+      pp.out[i] = out_disp[i0 + i];
+    }
+    rc = run(c, *pl, pp, m, keep && i0 == 0, (p.flags & STEREO_F_STAGE_TIMING) != 0, stream);
+    if (rc) return rc;
+  }
+  if (keep) c->last = pl;
+  return 0;
+}
+
+int stereo_disparity(stereo_ctx* c, const uint8_t* left, const uint8_t* right, int W, int H,
+                     int Dmax, const stereo_params* params, int16_t* out_disp, hipStream_t stream) {
+  if (!c) return STEREO_EINVAL;
+  return stereo_disparity_batch(c, &left, &right, 1, W, H, Dmax, params, &out_disp, stream);
+}
+
+int stereo_stage_times(stereo_ctx* c, double* ms, int* calls, int reset) {
+  if (!c) return STEREO_EINVAL;
+  c->err.clear();
+  if (!ms) return fail(c, STEREO_EINVAL, "null ms");
+  HIP_TRY(c, hipSetDevice(c->device));
+  for (int i = 0; i < STEREO_NUM_STAGES; ++i) ms[i] = 0.0;
+  const size_t per = STEREO_NUM_STAGES + 1;
+  for (int k = 0; k < c->timed_calls; ++k) {
+    hipEvent_t* ev = &c->events[(size_t)k * per];
+    HIP_TRY(c, hipEventSynchronize(ev[STEREO_NUM_STAGES]));
+    for (int i = 0; i < STEREO_NUM_STAGES; ++i) {
+      float t = 0.f;
+      HIP_TRY(c, hipEventElapsedTime(&t, ev[i], ev[i + 1]));
+      ms[i] += t;
+    }
+  }
+  if (calls) *calls = c->timed_calls;
+  if (reset) c->timed_calls = 0;
+  return 0;
+}
+
+int stereo_get_intermediate(stereo_ctx* c, int which, int d, void* dst, size_t bytes,
+                            hipStream_t stream) {
+  if (!c) return STEREO_EINVAL;
+  c->err.clear();
+  Plan* pl = c->last;
+  if (!pl) return fail(c, STEREO_EINVAL, "no call with STEREO_F_KEEP_INTERMEDIATES yet");
+  if (!dst) return fail(c, STEREO_EINVAL, "null destination");
+  HIP_TRY(c, hipSetDevice(c->device));
+  const size_t n = (size_t)pl->X * pl->Y;
+  auto need = [&](size_t b) { return bytes >= b; };
+  std::vector<uint16_t> tmp16;
+  switch (which) {
+    case STEREO_I_LUT: {
+      if (!need(263 * 2)) break;
+      std::memcpy(dst, pl->lut_ad, 256 * 2);
+      std::memcpy(static_cast<char*>(dst) + 512, pl->lut_mc, 7 * 2);
+      return 0;
+    }
+    case STEREO_I_HALF_L: case STEREO_I_HALF_R: case STEREO_I_CENSUS_L: case STEREO_I_CENSUS_R: {
+      if (!need(n)) break;
+      const int img = (which == STEREO_I_HALF_R || which == STEREO_I_CENSUS_R) ? 1 : 0;
+      tmp16.resize(n);
+      HIP_TRY(c, hipStreamSynchronize(stream));
+      HIP_TRY(c, hipMemcpy(tmp16.data(), pl->pk + img * n, n * 2, hipMemcpyDeviceToHost));
+      const bool census = which == STEREO_I_CENSUS_L || which == STEREO_I_CENSUS_R;
+      uint8_t* o = static_cast<uint8_t*>(dst);
+      for (size_t i = 0; i < n; ++i) o[i] = census ? (uint8_t)(tmp16[i] >> 8) : (uint8_t)(tmp16[i] & 255);
+      return 0;
+    }
+    case STEREO_I_ARMS_L: case STEREO_I_ARMS_R: {
+      if (!need(4 * n)) break;
+      HIP_TRY(c, hipStreamSynchronize(stream));
+      HIP_TRY(c, hipMemcpy(dst, pl->arms + (which == STEREO_I_ARMS_R ? n : 0), 4 * n,
+                           hipMemcpyDeviceToHost));
+      return 0;
+    }
+    case STEREO_I_COST_L_D: case STEREO_I_COST_R_D: case STEREO_I_CAX_L_D: case STEREO_I_CAX_R_D:
+    case STEREO_I_CA_L_D: case STEREO_I_CA_R_D: {
+      const bool cost = which == STEREO_I_COST_L_D || which == STEREO_I_COST_R_D;
+      if (!need(cost ? 2 * n : 4 * n)) break;
+      if (d < 0 || d >= pl->D) return fail(c, STEREO_EINVAL, "d %d outside 0..%d", d, pl->D - 1);
+      if (!pl->dbg_block) {
+        const size_t b = ((2 * n + 255) & ~size_t(255)) + 2 * ((4 * n + 255) & ~size_t(255));
+        hipError_t e = hipMalloc(&pl->dbg_block, b);
+        if (e != hipSuccess) {
+          (void)hipGetLastError();
+          return fail(c, STEREO_ENOMEM, "debug planes: %s", hipGetErrorString(e));
+        }
+        char* cur = static_cast<char*>(pl->dbg_block);
+        pl->dbg_cost = carve<uint16_t>(cur, n);
+        pl->dbg_cax = carve<uint32_t>(cur, n);
+        pl->dbg_ca = carve<uint32_t>(cur, n);
+      }
+      // one-disparity run of the fused kernel on pair 0 with the debug planes
+      // of the wanted base on; it overwrites the first d-chunk keys only
+      MatchArgs a = match_args(*pl, d, d + 1, 1);
+      a.dbg_cost = pl->dbg_cost; a.dbg_cax = pl->dbg_cax; a.dbg_ca = pl->dbg_ca;
+      a.dbg_base = (which == STEREO_I_COST_R_D || which == STEREO_I_CAX_R_D ||
+                    which == STEREO_I_CA_R_D) ? 1 : 0;
+      launch_match(*pl, a, 1, stream);
+      HIP_TRY(c, hipGetLastError());
+      HIP_TRY(c, hipStreamSynchronize(stream));
+      const void* src = cost ? (const void*)pl->dbg_cost
+                      : (which == STEREO_I_CAX_L_D || which == STEREO_I_CAX_R_D)
+                            ? (const void*)pl->dbg_cax : (const void*)pl->dbg_ca;
+      HIP_TRY(c, hipMemcpy(dst, src, cost ? 2 * n : 4 * n, hipMemcpyDeviceToHost));
+      return 0;
+    }
+    case STEREO_I_MINCOST_L: case STEREO_I_MINCOST_R: {
+      if (!need(4 * n)) break;
+      HIP_TRY(c, hipStreamSynchronize(stream));
+      HIP_TRY(c, hipMemcpy(dst, pl->mincost + (which == STEREO_I_MINCOST_R ? n : 0), 4 * n,
+                           hipMemcpyDeviceToHost));
+      return 0;
+    }
+    case STEREO_I_DISP_L: case STEREO_I_DISP_R: {
+      if (!need(2 * n)) break;
+      HIP_TRY(c, hipStreamSynchronize(stream));
+      HIP_TRY(c, hipMemcpy(dst, pl->disp + (which == STEREO_I_DISP_R ? n : 0), 2 * n,
+                           hipMemcpyDeviceToHost));
+      return 0;
+    }
+    case STEREO_I_GCP: {
+      if (!need(n)) break;
+      HIP_TRY(c, hipStreamSynchronize(stream));
+      HIP_TRY(c, hipMemcpy(dst, pl->gcp, n, hipMemcpyDeviceToHost));
+      return 0;
+    }
+    case STEREO_I_MEDIAN: case STEREO_I_FILLED: {
+      if (!need(2 * n)) break;
+      HIP_TRY(c, hipStreamSynchronize(stream));
+      HIP_TRY(c, hipMemcpy(dst, which == STEREO_I_MEDIAN ? pl->med : pl->filled, 2 * n,
+                           hipMemcpyDeviceToHost));
+      return 0;
+    }
+    default:
+      return fail(c, STEREO_EINVAL, "unknown intermediate %d", which);
+  }
+  return fail(c, STEREO_EINVAL, "destination of %zu bytes too small for intermediate %d", bytes,
+              which);
+}
+
+}  // extern "C"

@@ -1,0 +1,52 @@
+"""The C library loads and exports every entry point of include/stereo.h (no GPU)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2212_00488_amd as sm
+from paper_2212_00488_amd.build import LIB, ROOT
+
+HEADER = os.path.join(ROOT, "include", "stereo.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(stereo_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("stereo_create", "stereo_disparity", "stereo_destroy", "stereo_default_params",
+              "stereo_disparity_batch", "stereo_get_intermediate", "stereo_last_error"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    L = ctypes.CDLL(LIB)
+    for n in declared_functions():
+        assert hasattr(L, n), n
+
+
+def test_default_params_are_the_papers():
+    if not os.path.exists(LIB):
+        pytest.skip("library not built")
+    p = sm.default_params()
+    assert p.size == ctypes.sizeof(sm.Params) == 36
+    assert abs(p.lambda_ad - 0.3) < 1e-6 and abs(p.lambda_mc - 2.3) < 1e-6
+    assert (p.cost_scale, p.color_delta, p.arm_x, p.arm_y, p.fill_T, p.flags) == (
+        1024, 13, 21, 31, 3, 0)
+
+
+def test_intermediate_ids_match_header():
+    text = open(HEADER).read()
+    ids = dict((k.lower(), int(v)) for k, v in re.findall(r"STEREO_I_([A-Z_]+)\s*=\s*(\d+)", text))
+    from paper_2212_00488_amd.binding import INTERMEDIATES, I_LUT
+    for name, (which, _, _) in INTERMEDIATES.items():
+        assert ids[name] == which, name
+    assert ids["lut"] == I_LUT
