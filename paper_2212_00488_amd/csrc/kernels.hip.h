@@ -18,14 +18,8 @@ constexpr int kMaxPairs = 8;      // pairs per launch (batched entry point)
 constexpr int kTX = 64;           // k_match strip width = one wave
 constexpr int kWaves = 16;        // k_match workgroup = 16 waves
 constexpr int kThreads = kWaves * 64;
-constexpr int kKMax = 36;         // most output rows per k_match thread (band <= 576 rows)
-constexpr int kTab = 7 * 256;     // combined cost table [census distance][abs diff]
+constexpr int kKMax = 34;         // most output rows per k_match thread (band <= 544 rows)
 constexpr int kLdsBytes = 163840; // LDS per workgroup on gfx950
-
-// Rows of the k_match LDS plane for a given number of 64-column sub-passes.
-__host__ __device__ constexpr int plane_rows(int nsub) {
-  return (kLdsBytes - kTab * 2 - kWaves * 64 * 4 - kWaves * nsub * 64 * 4) / 256 - 2;
-}
 
 struct PairPtrs {
   const uint8_t* left[kMaxPairs];
@@ -62,40 +56,75 @@ __global__ void __launch_bounds__(256) k_prep(PairPtrs pp, int W, int H, int X, 
 }
 
 // ---------------------------------------------------------------- k_feat
-// One thread per half-res pixel of one image.  Writes
-//   pk[img][y][x]   = gray | census << 8   (census: 6 neighbours in three rows,
-//                     bit k = [neighbour < centre], borders clamped)
-//   arms[img][y][x] = m | n << 8 | M << 16 | N << 24  (contiguous pixels with
-//                     |I - I(centre)| < delta, capped per side and at the border)
+// Packed half-res pixel used by k_match: gray * 2 in bits 0..9 and the census
+// string in bits 16..21.  Columns outside the image hold kSentinel, whose
+// brightness difference to any pixel exceeds 255, so that the cost table
+// returns C_max there (the x - d < 0 / x + d >= X convention) without a branch.
+constexpr uint32_t kSentinel = 1022u;
+constexpr int kFeatRows = 16;    // output rows per k_feat workgroup
+constexpr int kMaxArm = 127;
+
+// One workgroup = 64 columns x 16 rows of one image, 256 threads (64 x 4).
+// Two LDS tiles of the half image (borders clamped): rows y0-1..y0+16 over
+// the columns reachable by the horizontal arms and the census, and rows
+// y0-arm_y..y0+15+arm_y over the 64 columns for the vertical arms.
+//   census: 6 neighbours in three rows, bit k = [neighbour < centre]
+//   arms  : contiguous pixels with |I - I(centre)| < delta, capped per side
+//           and at the image border; packed m | n<<8 | M<<16 | N<<24
+// grid: (ceil(X/64), ceil(Y/16), 2 * npair), block (64, 4).
 __global__ void __launch_bounds__(256) k_feat(const uint8_t* __restrict__ half, int X, int Y,
-                                              int delta, int arm_x, int arm_y,
-                                              uint16_t* __restrict__ pk,
+                                              int delta, int arm_x, int arm_y, int XP, int pad,
+                                              int XA, uint32_t* __restrict__ pk,
                                               uint32_t* __restrict__ arms) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
-  const int img = blockIdx.z;
-  if (x >= X || y >= Y) return;
+  constexpr int TXW = 64 + 2 * (kMaxArm + 2);
+  __shared__ uint8_t tx[kFeatRows + 2][TXW];
+  __shared__ uint8_t ty[kFeatRows + 2 * kMaxArm][64];
+  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kFeatRows, img = blockIdx.z;
+  const int t = threadIdx.y * 64 + threadIdx.x;
   const uint8_t* h = half + (size_t)img * X * Y;
-  const int c = h[(size_t)y * X + x];
-  const int ym = clampi(y - 1, 0, Y - 1), yp = clampi(y + 1, 0, Y - 1);
-  const int xm1 = clampi(x - 1, 0, X - 1), xp1 = clampi(x + 1, 0, X - 1);
-  const int xm2 = clampi(x - 2, 0, X - 1), xp2 = clampi(x + 2, 0, X - 1);
-  int bits = 0;
-  bits |= (h[(size_t)ym * X + xm1] < c) << 0;
-  bits |= (h[(size_t)ym * X + xp1] < c) << 1;
-  bits |= (h[(size_t)y * X + xm2] < c) << 2;
-  bits |= (h[(size_t)y * X + xp2] < c) << 3;
-  bits |= (h[(size_t)yp * X + xm1] < c) << 4;
-  bits |= (h[(size_t)yp * X + xp1] < c) << 5;
-  const uint8_t* row = h + (size_t)y * X;
-  int m = 0, n = 0, M = 0, N = 0;
-  while (m < arm_x && x - m - 1 >= 0 && iabs(row[x - m - 1] - c) < delta) ++m;
-  while (n < arm_x && x + n + 1 < X && iabs(row[x + n + 1] - c) < delta) ++n;
-  while (M < arm_y && y - M - 1 >= 0 && iabs(h[(size_t)(y - M - 1) * X + x] - c) < delta) ++M;
-  while (N < arm_y && y + N + 1 < Y && iabs(h[(size_t)(y + N + 1) * X + x] - c) < delta) ++N;
-  const size_t o = (size_t)img * X * Y + (size_t)y * X + x;
-  pk[o] = (uint16_t)(c | (bits << 8));
-  arms[o] = (uint32_t)m | ((uint32_t)n << 8) | ((uint32_t)M << 16) | ((uint32_t)N << 24);
+  const int hx = arm_x + 2, wx = 64 + 2 * hx;
+  for (int i = t; i < (kFeatRows + 2) * wx; i += 256) {
+    const int r = i / wx, c = i - r * wx;
+    tx[r][c] = h[(size_t)clampi(y0 - 1 + r, 0, Y - 1) * X + clampi(x0 - hx + c, 0, X - 1)];
+  }
+  const int hy = kFeatRows + 2 * arm_y;
+  for (int i = t; i < hy * 64; i += 256) {
+    const int r = i >> 6, c = i & 63;
+    ty[r][c] = h[(size_t)clampi(y0 - arm_y + r, 0, Y - 1) * X + clampi(x0 + c, 0, X - 1)];
+  }
+  __syncthreads();
+  const int lx = threadIdx.x, x = x0 + lx;
+  if (x >= X) return;
+  for (int k = 0; k < kFeatRows / 4; ++k) {
+    const int ly = threadIdx.y + 4 * k, y = y0 + ly;
+    if (y >= Y) break;
+    const uint8_t* row = &tx[ly + 1][hx + lx];   // row[i] = I(x + i, y)
+    const int c = row[0];
+    int bits = 0;
+    bits |= (tx[ly][hx + lx - 1] < c) << 0;
+    bits |= (tx[ly][hx + lx + 1] < c) << 1;
+    bits |= (row[-2] < c) << 2;
+    bits |= (row[2] < c) << 3;
+    bits |= (tx[ly + 2][hx + lx - 1] < c) << 4;
+    bits |= (tx[ly + 2][hx + lx + 1] < c) << 5;
+    int m = 0, n = 0, M = 0, N = 0;
+    while (m < arm_x && x - m - 1 >= 0 && iabs(row[-m - 1] - c) < delta) ++m;
+    while (n < arm_x && x + n + 1 < X && iabs(row[n + 1] - c) < delta) ++n;
+    const int cy = ly + arm_y;                    // ty row of (x, y)
+    while (M < arm_y && y - M - 1 >= 0 && iabs(ty[cy - M - 1][lx] - c) < delta) ++M;
+    while (N < arm_y && y + N + 1 < Y && iabs(ty[cy + N + 1][lx] - c) < delta) ++N;
+    pk[((size_t)img * Y + y) * XP + pad + x] = (uint32_t)(2 * c) | ((uint32_t)bits << 16);
+    arms[((size_t)img * Y + y) * XA + x] =
+        (uint32_t)m | ((uint32_t)n << 8) | ((uint32_t)M << 16) | ((uint32_t)N << 24);
+  }
+}
+
+// Fills the padded pk planes with kSentinel (run once when a plan is made;
+// k_feat later overwrites the image columns).
+__global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
 }
 
 // ---------------------------------------------------------------- k_match
@@ -115,13 +144,30 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
 // the LDS itself serves the accesses of a wave in issue order.
 #define WAVE_LDS_ORDER() __asm__ volatile("" ::: "memory")
 
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), (short)0, (int)bytes,
+                                           0x00020000);
+}
+
+// cost table [census distance h][signed brightness difference + 512]: 7 rows
+// of 1024 entries; |difference| > 255 only arises against the sentinel
+constexpr int kTab = 7 * 1024;
+
+// LDS rows of the k_match plane for NS sub-passes of 128 row-buffer columns.
+__host__ __device__ constexpr int plane_rows(int ns) {
+  return (kLdsBytes - kTab * 2 - kWaves * 64 * 4 - kWaves * ns * 128 * 4) / 256 - 2;
+}
+
 struct MatchArgs {
-  const uint16_t* pk;     // [2*npair][Y][X]  gray | census << 8
-  const uint32_t* arms;   // [2*npair][Y][X]
-  const uint16_t* tab;    // [7][256] combined cost table
+  const uint32_t* pk;     // [2*npair][Y][XP]  padded: gray*2 | census << 16
+  const uint32_t* arms;   // [2*npair][Y][XA]  zero past column X
+  const uint16_t* tab;    // [7][1024]
   uint32_t* keys;         // [npair][nchunk][2][Y][X]  (min CA) << 8 | argmin d
-  int X, Y, arm_x, arm_y, cmax;
+  int X, Y, XP, pad, XA, arm_x, arm_y;
   int nbands, nchunk, dlo, dhi;
+  uint32_t pk_bytes, arms_bytes;  // sizes of the pk and arms buffers
   // debug planes (pair 0, the single disparity dlo; NULL in the fast path)
   uint16_t* dbg_cost;
   uint32_t* dbg_cax;
@@ -130,28 +176,31 @@ struct MatchArgs {
 };
 
 // One workgroup = one 64-column strip x one band of rows x one base image
-// x one chunk of disparities.  For each d of the chunk:
-//   row pass   : each wave takes rows of the band; C (Eq. 3-5, table lookup) over
-//                the strip plus arm_x+1 columns either side, inclusive wave scan,
-//                CA_x = P[x+n] - P[x-m-1] (Eq. 7) into the LDS plane;
+// x one chunk of disparities; 16 waves.  For each d of the chunk:
+//   row pass   : each wave takes rows of the band; every lane evaluates the
+//                cost (Eq. 3-5, one lookup in a table indexed by census distance
+//                and signed brightness difference) of two adjacent columns of
+//                the strip plus arm_x+1 (rounded up to even) columns on either
+//                side, an inclusive wave scan gives the row prefix P, and
+//                CA_x = P[x+n] - P[x-m-1] (Eq. 7) goes into the LDS plane;
 //   column pass: segmented prefix down each column of the plane, in place, then
 //                CA = Q[y+N] - Q[y-M-1] (Eq. 8) for the band's output rows and
 //                key = min(key, CA << 8 | d): the smallest d wins ties (Step5).
 // The right-based cost is evaluated as cost(R(x), L(x+d)), which is C^L(x+d)
 // of Eq. 6 term for term.  Sums wrap modulo 2^32; every difference taken is a
-// window sum below 2^24, hence exact.
-// KMAX (<= kKMax) bounds the output rows per thread: a band has at most
-// 16 * KMAX output rows.
+// window sum below 2^24, hence exact.  KMAX (<= kKMax) bounds the output rows
+// per thread: a band has at most 16 * KMAX output rows.
 // grid: (nstrips, nbands * nchunk, 2 * npair), block 1024.
-template <int NSUB, int KMAX>
+template <int NS, int KMAX>
 __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
-  constexpr int PR = plane_rows(NSUB);
+  constexpr int PR = plane_rows(NS);
   __shared__ uint16_t s_tab[kTab];
-  __shared__ uint32_t s_row[kWaves][NSUB * 64];
+  __shared__ uint32_t s_row[kWaves][NS * 128];
   __shared__ uint32_t s_seg[kWaves][64];
   __shared__ uint32_t s_plane[(PR + 1) * 64];  // row 0 = zeros (band row -1)
 
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: row offsets stay scalar
   const int X = a.X, Y = a.Y;
   const int x0 = blockIdx.x * kTX;
   const int band = blockIdx.y % a.nbands, chunk = blockIdx.y / a.nbands;
@@ -162,12 +211,13 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   const int nb = yb - ya, o0 = y0 - ya, o1 = y1 - ya;
   const int span = a.dhi - a.dlo;
   const int d0 = a.dlo + (chunk * span) / a.nchunk, d1 = a.dlo + ((chunk + 1) * span) / a.nchunk;
-  const int hx = a.arm_x + 1;          // first column of the row buffer is x0 - hx
+  const int hx = (a.arm_x + 2) & ~1;   // row buffer starts at column x0 - hx (even)
   const int sgn = base ? 1 : -1;       // other-image column is x + sgn * d
   const size_t plane = (size_t)X * Y;
-  const uint16_t* pkb = a.pk + (size_t)(2 * pair + base) * plane;
-  const uint16_t* pko = a.pk + (size_t)(2 * pair + (base ^ 1)) * plane;
-  const uint32_t* armb = a.arms + (size_t)(2 * pair + base) * plane;
+  const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(a.pk, a.pk_bytes);
+  const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(a.arms, a.arms_bytes);
+  const uint32_t img_b = (uint32_t)(2 * pair + base), img_o = (uint32_t)(2 * pair + (base ^ 1));
+  const uint32_t pkrow = (uint32_t)a.XP * 4u, armrow = (uint32_t)a.XA * 4u;
   const bool dbg = a.dbg_cost != nullptr && pair == 0 && base == a.dbg_base;
 
   for (int i = t; i < kTab; i += kThreads) s_tab[i] = a.tab[i];
@@ -188,61 +238,67 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
     key[k] = 0xffffffffu;
     uint32_t mn = 0u;
     const int r = o0 + wave + k * kWaves;
-    if (x < X && r < o1) mn = armb[(size_t)(ya + r) * X + x] >> 16;
+    if (x < X && r < o1) mn = a.arms[((size_t)img_b * Y + ya + r) * a.XA + x] >> 16;
     if (k & 1) marm[k / 2] |= mn << 16;
     else marm[k / 2] = mn;
   }
   // plane word of (band row o0 + wave, column c); plane row = band row + 1
   const int fin_base = (o0 + wave + 1) * 64 + c;
+  // byte offset of this lane's first column pair inside a padded pk row
+  const uint32_t vb = (uint32_t)(a.pad + x0 - hx + 2 * lane) * 4u;
   __syncthreads();
 
   for (int d = d0; d < d1; ++d) {
+    const uint32_t vo = vb + (uint32_t)(sgn * d * 4);
     // ---- row pass
     for (int r = wave; r < nb; r += kWaves) {
-      const int y = ya + r;
-      const uint16_t* rb = pkb + (size_t)y * X;
-      const uint16_t* ro = pko + (size_t)y * X;
+      const uint32_t y = (uint32_t)(ya + r);
+      const uint32_t sb = (img_b * (uint32_t)Y + y) * pkrow;
+      const uint32_t so = (img_o * (uint32_t)Y + y) * pkrow;
+      const uint32_t am = __builtin_amdgcn_raw_buffer_load_b32(
+          ra, (uint32_t)x * 4u, (img_b * (uint32_t)Y + y) * armrow, 0);
       uint32_t carry = 0;
 #pragma unroll
-      for (int j = 0; j < NSUB; ++j) {
-        const int xc = x0 - hx + j * 64 + lane;
-        uint32_t cst = 0;
-        if (xc >= 0 && xc < X) {
-          const int xo = xc + sgn * d;
-          if (xo < 0 || xo >= X) {
-            cst = (uint32_t)a.cmax;
-          } else {
-            const uint32_t b = rb[xc], o = ro[xo];
-            const int ad = iabs((int)(b & 255u) - (int)(o & 255u));
-            const int hd = __builtin_popcount((b ^ o) >> 8);
-            cst = s_tab[hd * 256 + ad];
-          }
-          if (dbg && d == a.dlo && xc >= x0 && xc < x0 + kTX && y >= y0 && y < y1)
-            a.dbg_cost[(size_t)y * X + xc] = (uint16_t)cst;
+      for (int s = 0; s < NS; ++s) {
+        const u32x2 bv = __builtin_amdgcn_raw_buffer_load_b64(rb, vb + s * 512, sb, 0);
+        const u32x2 ov = __builtin_amdgcn_raw_buffer_load_b64(rb, vo + s * 512, so, 0);
+        // byte offset of entry (h, 512 + diff): h * 2048 + 2 * diff + 1024, and the
+        // stored grays are already doubled
+        const int e0 = ((int)__builtin_popcount((bv.x ^ ov.x) >> 16) << 11) +
+                       ((int)(bv.x & 0xffffu) - (int)(ov.x & 0xffffu));
+        const int e1 = ((int)__builtin_popcount((bv.y ^ ov.y) >> 16) << 11) +
+                       ((int)(bv.y & 0xffffu) - (int)(ov.y & 0xffffu));
+        const char* tb = reinterpret_cast<const char*>(s_tab) + 1024;
+        const uint32_t c0 = *reinterpret_cast<const uint16_t*>(tb + e0);
+        const uint32_t c1 = *reinterpret_cast<const uint16_t*>(tb + e1);
+        const uint32_t p1 = wave_scan_incl(c0 + c1) + carry;
+        if (NS > 1) carry = __builtin_amdgcn_readlane(p1, 63);
+        *reinterpret_cast<u32x2*>(&s_row[wave][s * 128 + 2 * lane]) = u32x2{p1 - c1, p1};
+        if (dbg && d == a.dlo && (int)y >= y0 && (int)y < y1) {
+          const int xc = x0 - hx + s * 128 + 2 * lane;
+          if (xc >= x0 && xc < x0 + kTX && xc < X) a.dbg_cost[(size_t)y * X + xc] = (uint16_t)c0;
+          if (xc + 1 >= x0 && xc + 1 < x0 + kTX && xc + 1 < X)
+            a.dbg_cost[(size_t)y * X + xc + 1] = (uint16_t)c1;
         }
-        const uint32_t p = wave_scan_incl(cst) + carry;
-        carry = __builtin_amdgcn_readlane(p, 63);
-        s_row[wave][j * 64 + lane] = p;
       }
       WAVE_LDS_ORDER();
-      uint32_t cax = 0;
-      if (x < X) {
-        const uint32_t am = armb[(size_t)y * X + x];
-        const int m = am & 255u, n = (am >> 8) & 255u;
-        cax = s_row[wave][lane + hx + n] - s_row[wave][lane + hx - m - 1];
-        if (dbg && d == a.dlo && y >= y0 && y < y1) a.dbg_cax[(size_t)y * X + x] = cax;
-      }
+      const int m = am & 255u, n = (am >> 8) & 255u;
+      const uint32_t cax = s_row[wave][lane + hx + n] - s_row[wave][lane + hx - m - 1];
+      if (dbg && d == a.dlo && x < X && (int)y >= y0 && (int)y < y1)
+        a.dbg_cax[(size_t)y * X + x] = cax;
       s_plane[(r + 1) * 64 + lane] = cax;
       WAVE_LDS_ORDER();
     }
     __syncthreads();
     // ---- column pass: segment sums, segment offsets, prefix in place
     uint32_t acc = 0;
+#pragma unroll 8
     for (int r = r0; r < r1; ++r) acc += s_plane[(r + 1) * 64 + c];
     s_seg[wave][c] = acc;
     __syncthreads();
     uint32_t off = 0;
     for (int s = 0; s < wave; ++s) off += s_seg[s][c];
+#pragma unroll 8
     for (int r = r0; r < r1; ++r) {
       off += s_plane[(r + 1) * 64 + c];
       s_plane[(r + 1) * 64 + c] = off;
@@ -347,8 +403,8 @@ __device__ __forceinline__ int median9(int* v) {
 
 __global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp,
                                                 const uint8_t* __restrict__ gcp,
-                                                const uint16_t* __restrict__ pk, int X, int Y,
-                                                int T, int16_t* __restrict__ med_out,
+                                                const uint32_t* __restrict__ pk, int XP, int pad,
+                                                int X, int Y, int T, int16_t* __restrict__ med_out,
                                                 int16_t* __restrict__ filled) {
   __shared__ int16_t s_med[4096];
   __shared__ uint8_t s_g[4096];
@@ -369,7 +425,7 @@ __global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp
     s_med[x] = (int16_t)m;
     if (med_out) med_out[(size_t)pair * plane + (size_t)y * X + x] = (int16_t)m;
     s_g[x] = gcp[(size_t)pair * plane + (size_t)y * X + x];
-    s_h[x] = (uint8_t)(pk[(size_t)(2 * pair) * plane + (size_t)y * X + x] & 255u);
+    s_h[x] = (uint8_t)((pk[((size_t)(2 * pair) * Y + y) * XP + pad + x] & 1023u) >> 1);
   }
   __syncthreads();
   // nearest GCP to the left / right: contiguous segments per thread + scans

@@ -32,14 +32,15 @@ struct Plan {
   stereo_params p{};
   uint16_t lut_ad[256]{}, lut_mc[7]{};
   int cmax = 0;
-  int nsub = 2, kmax = 8, nstrips = 0, nbands = 0, nchunk = 0;
+  int ns = 1, kmax = 8, nstrips = 0, nbands = 0, nchunk = 0;
+  int XP = 0, pad = 0, XA = 0;  // padded pitches of pk and arms
   size_t bytes = 0;
   // device memory, one block carved into planes
   void* block = nullptr;
   uint8_t* half = nullptr;    // [2*npair][Y][X]
-  uint16_t* pk = nullptr;     // [2*npair][Y][X]
-  uint32_t* arms = nullptr;   // [2*npair][Y][X]
-  uint16_t* tab = nullptr;    // [7][256]
+  uint32_t* pk = nullptr;     // [2*npair][Y][XP]  gray*2 | census<<16, kSentinel padding
+  uint32_t* arms = nullptr;   // [2*npair][Y][XA]  zero padding
+  uint16_t* tab = nullptr;    // [7][512]
   uint32_t* keys = nullptr;   // [npair][nchunk][2][Y][X]
   int16_t* disp = nullptr;    // [2*npair][Y][X]
   uint32_t* mincost = nullptr;// [2*npair][Y][X]
@@ -132,15 +133,15 @@ T* carve(char*& cur, size_t count) {
 // Launch geometry: bands keep the k_match LDS plane and the per-thread key
 // registers within bounds; d-chunks raise the workgroup count to fill the CUs.
 void plan_geometry(Plan& pl, int num_cu) {
-  pl.nsub = (65 + 2 * pl.p.arm_x + 63) / 64;
-  if (pl.nsub < 2) pl.nsub = 2;
-  const int pr = plane_rows(pl.nsub);
+  // the row buffer spans x0 - hx .. x0 + 63 + arm_x, hx = arm_x + 1 rounded up to even
+  pl.ns = (66 + 2 * pl.p.arm_x + 127) / 128;
+  const int pr = plane_rows(pl.ns);
   // Output rows of a band are spread over the 16 waves, KMAX per thread
   // (template steps 8..36).  The finalize of a band reads plane rows up to
   // o0 + 16 KMAX (padding rows included, o0 <= arm_y is the top halo), and
   // the band itself must fit the plane.
   auto kstep = [](int rows_per_thread) {
-    for (int s : {8, 16, 24, 32, kKMax})
+    for (int s : {8, 16, 24, 32, kKMax})  // kKMax = 34
       if (rows_per_thread <= s) return s;
     return -1;
   };
@@ -156,6 +157,11 @@ void plan_geometry(Plan& pl, int num_cu) {
   pl.kmax = km;
   pl.nbands = nb;
   pl.nstrips = (pl.X + kTX - 1) / kTX;
+  // pk padding covers every column a k_match lane loads: x0 - hx - D at the
+  // left, x0 - hx + 128 NS - 1 + D < X + 128 NS + D at the right
+  pl.pad = ((128 * pl.ns + pl.D + 2) + 3) & ~3;
+  pl.XP = pl.X + 2 * pl.pad;
+  pl.XA = pl.nstrips * kTX;
   const int per_chunk = pl.nstrips * pl.nbands * 2 * pl.npair;
   // one k_match workgroup fits a CU at a time (LDS): split d into as many
   // chunks as one round of CUs holds, at most D; each extra chunk costs one
@@ -174,7 +180,8 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
   plan_geometry(*pl, c->num_cu);
   const size_t n = (size_t)pl->X * pl->Y;
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  size_t bytes = al(2 * npair * n) + al(2 * npair * n * 2) + al(2 * npair * n * 4) + al(kTab * 2) +
+  const size_t npk = (size_t)2 * npair * pl->Y * pl->XP, nar = (size_t)2 * npair * pl->Y * pl->XA;
+  size_t bytes = al(2 * npair * n) + al(npk * 4) + al(nar * 4) + al(kTab * 2) +
                  al((size_t)npair * pl->nchunk * 2 * n * 4) + al(2 * npair * n * 2) +
                  al(2 * npair * n * 4) + al(npair * n) + al(npair * n * 2) + al(npair * n * 2);
   if (c->mem_cap && c->used + bytes > c->mem_cap) {
@@ -191,8 +198,8 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
   pl->bytes = bytes;
   char* cur = static_cast<char*>(pl->block);
   pl->half = carve<uint8_t>(cur, 2 * npair * n);
-  pl->pk = carve<uint16_t>(cur, 2 * npair * n);
-  pl->arms = carve<uint32_t>(cur, 2 * npair * n);
+  pl->pk = carve<uint32_t>(cur, npk);
+  pl->arms = carve<uint32_t>(cur, nar);
   pl->tab = carve<uint16_t>(cur, kTab);
   pl->keys = carve<uint32_t>(cur, (size_t)npair * pl->nchunk * 2 * n);
   pl->disp = carve<int16_t>(cur, 2 * npair * n);
@@ -200,13 +207,24 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
   pl->gcp = carve<uint8_t>(cur, npair * n);
   pl->med = carve<int16_t>(cur, npair * n);
   pl->filled = carve<int16_t>(cur, npair * n);
-  uint16_t tab[kTab];
-  for (int h = 0; h < 7; ++h)
-    for (int a = 0; a < 256; ++a) tab[h * 256 + a] = (uint16_t)(pl->lut_ad[a] + pl->lut_mc[h]);
+  // table [census distance h][512 + signed brightness difference]: differences
+  // beyond +-255 only arise against the padding sentinel and cost C_max
+  static uint16_t tab[kTab];
+  for (int hd = 0; hd < 7; ++hd)
+    for (int i = 0; i < 1024; ++i) {
+      const int a = i < 512 ? 512 - i : i - 512;
+      tab[hd * 1024 + i] = (uint16_t)(a < 256 ? pl->lut_ad[a] + pl->lut_mc[hd] : pl->cmax);
+    }
   e = hipMemcpy(pl->tab, tab, sizeof tab, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(pl->arms, 0, nar * 4);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, nullptr, pl->pk, npk, kSentinel);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_plan(pl);
-    return fail(c, STEREO_EHIP, "hipMemcpy(tab): %s", hipGetErrorString(e));
+    return fail(c, STEREO_EHIP, "plan initialisation: %s", hipGetErrorString(e));
   }
   c->used += bytes;
   *out = pl;
@@ -245,7 +263,10 @@ int get_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int 
 MatchArgs match_args(const Plan& pl, int dlo, int dhi, int nchunk) {
   MatchArgs a{};
   a.pk = pl.pk; a.arms = pl.arms; a.tab = pl.tab; a.keys = pl.keys;
-  a.X = pl.X; a.Y = pl.Y; a.arm_x = pl.p.arm_x; a.arm_y = pl.p.arm_y; a.cmax = pl.cmax;
+  a.X = pl.X; a.Y = pl.Y; a.XP = pl.XP; a.pad = pl.pad; a.XA = pl.XA;
+  a.arm_x = pl.p.arm_x; a.arm_y = pl.p.arm_y;
+  a.pk_bytes = (uint32_t)((size_t)2 * pl.npair * pl.Y * pl.XP * 4);
+  a.arms_bytes = (uint32_t)((size_t)2 * pl.npair * pl.Y * pl.XA * 4);
   a.nbands = pl.nbands; a.nchunk = nchunk; a.dlo = dlo; a.dhi = dhi;
   return a;
 }
@@ -263,11 +284,10 @@ void launch_match_k(const Plan& pl, const MatchArgs& a, dim3 grid, hipStream_t s
 
 void launch_match(const Plan& pl, const MatchArgs& a, int npair, hipStream_t s) {
   dim3 grid(pl.nstrips, pl.nbands * a.nchunk, 2 * npair);
-  switch (pl.nsub) {
+  switch (pl.ns) {
+    case 1: launch_match_k<1>(pl, a, grid, s); break;
     case 2: launch_match_k<2>(pl, a, grid, s); break;
-    case 3: launch_match_k<3>(pl, a, grid, s); break;
-    case 4: launch_match_k<4>(pl, a, grid, s); break;
-    default: launch_match_k<5>(pl, a, grid, s); break;
+    default: launch_match_k<3>(pl, a, grid, s); break;
   }
 }
 
@@ -298,16 +318,17 @@ int run(stereo_ctx* c, Plan& pl, const PairPtrs& pp, int npair, bool keep, bool 
   hipLaunchKernelGGL(k_prep, dim3((X + 63) / 64, (Y + 3) / 4, 2 * npair), b2, 0, s, pp, pl.W,
                      pl.H, X, Y, pl.half);
   mark(1);
-  hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + 3) / 4, 2 * npair), b2, 0, s, pl.half, X, Y,
-                     pl.p.color_delta, pl.p.arm_x, pl.p.arm_y, pl.pk, pl.arms);
+  hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + kFeatRows - 1) / kFeatRows, 2 * npair), b2, 0,
+                     s, pl.half, X, Y, pl.p.color_delta, pl.p.arm_x, pl.p.arm_y, pl.XP, pl.pad,
+                     pl.XA, pl.pk, pl.arms);
   mark(2);
   launch_match(pl, match_args(pl, 0, pl.D, pl.nchunk), npair, s);
   mark(3);
   hipLaunchKernelGGL(k_wta_cc, dim3(Y, npair), dim3(256), 0, s, pl.keys, pl.nchunk, X, Y, pl.disp,
                      keep ? pl.mincost : nullptr, pl.gcp);
   mark(4);
-  hipLaunchKernelGGL(k_refine, dim3(Y, npair), dim3(256), 0, s, pl.disp, pl.gcp, pl.pk, X, Y,
-                     pl.p.fill_T, keep ? pl.med : nullptr, pl.filled);
+  hipLaunchKernelGGL(k_refine, dim3(Y, npair), dim3(256), 0, s, pl.disp, pl.gcp, pl.pk, pl.XP,
+                     pl.pad, X, Y, pl.p.fill_T, keep ? pl.med : nullptr, pl.filled);
   mark(5);
   hipLaunchKernelGGL(k_upscale, dim3((pl.W + 63) / 64, (pl.H + 3) / 4, npair), b2, 0, s, pp,
                      pl.filled, pl.W, pl.H, X, Y, pl.p.fill_T);
@@ -451,7 +472,6 @@ int stereo_get_intermediate(stereo_ctx* c, int which, int d, void* dst, size_t b
   HIP_TRY(c, hipSetDevice(c->device));
   const size_t n = (size_t)pl->X * pl->Y;
   auto need = [&](size_t b) { return bytes >= b; };
-  std::vector<uint16_t> tmp16;
   switch (which) {
     case STEREO_I_LUT: {
       if (!need(263 * 2)) break;
@@ -462,19 +482,23 @@ int stereo_get_intermediate(stereo_ctx* c, int which, int d, void* dst, size_t b
     case STEREO_I_HALF_L: case STEREO_I_HALF_R: case STEREO_I_CENSUS_L: case STEREO_I_CENSUS_R: {
       if (!need(n)) break;
       const int img = (which == STEREO_I_HALF_R || which == STEREO_I_CENSUS_R) ? 1 : 0;
-      tmp16.resize(n);
+      std::vector<uint32_t> tmp(n);
       HIP_TRY(c, hipStreamSynchronize(stream));
-      HIP_TRY(c, hipMemcpy(tmp16.data(), pl->pk + img * n, n * 2, hipMemcpyDeviceToHost));
+      HIP_TRY(c, hipMemcpy2D(tmp.data(), (size_t)pl->X * 4,
+                             pl->pk + (size_t)img * pl->Y * pl->XP + pl->pad, (size_t)pl->XP * 4,
+                             (size_t)pl->X * 4, pl->Y, hipMemcpyDeviceToHost));
       const bool census = which == STEREO_I_CENSUS_L || which == STEREO_I_CENSUS_R;
       uint8_t* o = static_cast<uint8_t*>(dst);
-      for (size_t i = 0; i < n; ++i) o[i] = census ? (uint8_t)(tmp16[i] >> 8) : (uint8_t)(tmp16[i] & 255);
+      for (size_t i = 0; i < n; ++i)
+        o[i] = census ? (uint8_t)((tmp[i] >> 16) & 63u) : (uint8_t)((tmp[i] & 1023u) >> 1);
       return 0;
     }
     case STEREO_I_ARMS_L: case STEREO_I_ARMS_R: {
       if (!need(4 * n)) break;
+      const int img = which == STEREO_I_ARMS_R ? 1 : 0;
       HIP_TRY(c, hipStreamSynchronize(stream));
-      HIP_TRY(c, hipMemcpy(dst, pl->arms + (which == STEREO_I_ARMS_R ? n : 0), 4 * n,
-                           hipMemcpyDeviceToHost));
+      HIP_TRY(c, hipMemcpy2D(dst, (size_t)pl->X * 4, pl->arms + (size_t)img * pl->Y * pl->XA,
+                             (size_t)pl->XA * 4, (size_t)pl->X * 4, pl->Y, hipMemcpyDeviceToHost));
       return 0;
     }
     case STEREO_I_COST_L_D: case STEREO_I_COST_R_D: case STEREO_I_CAX_L_D: case STEREO_I_CAX_R_D:
