@@ -138,9 +138,9 @@ int stereo_get_intermediate(stereo_ctx* ctx, int which, int d, void* dst, size_t
                             hipStream_t stream);
 
 /* Device time of each stage, in the order of Sec. IV: 0 downscale (Step1),
- * 1 census + arms (Step2, Step4), 2 cost + x/y aggregation + WTA (Step3,
- * Step5), 3 chunk minimum + cross-check (Step6), 4 median + filling (Step7),
- * 5 upscale (Step8).  Sums, in milliseconds, over the calls made with
+ * 1 census + arms (Step2, Step4), 2 cost + x/y aggregation + WTA per
+ * d-chunk (Step3, Step5), 3 minimum over the d-chunks (Step5), 4 cross-check
+ * + median + filling (Step6, Step7), 5 upscale (Step8).  Sums, in milliseconds, over the calls made with
  * STEREO_F_STAGE_TIMING since the last reset, measured by HIP events
  * recorded on each call's stream around each stage's launch.  ms receives
  * STEREO_NUM_STAGES values; *calls (may be NULL) the number of calls.

@@ -18,8 +18,8 @@ from .build import LIB
 OK, EINVAL, ENOMEM, EHIP, EUNIMPL = 0, -1, -2, -3, -4
 F_KEEP_INTERMEDIATES = 1
 F_STAGE_TIMING = 2
-STAGES = ("downscale", "census_arms", "cost_aggregate_wta", "chunk_min_crosscheck",
-          "median_fill", "upscale")
+STAGES = ("downscale", "census_arms", "cost_aggregate_wta", "chunk_min",
+          "crosscheck_median_fill", "upscale")
 
 # stereo_intermediate: id -> (dtype, trailing dims)
 INTERMEDIATES = {

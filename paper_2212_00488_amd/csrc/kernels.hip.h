@@ -5,8 +5,8 @@
 //   k_feat     mini-census + cross arms of both half images    (Sec. III-B, III-C)
 //   k_match    cost, x- and y-aggregation and WTA, fused: the  (Eq. 3-9)
 //              cost volume never leaves the chip
-//   k_wta_cc   combine the d-chunk minima, cross-check         (Eq. 9-10)
-//   k_refine   3x3 median and bilateral filling of non-GCPs    (Sec. III-E, Eq. 11)
+//   k_wta      combine the d-chunk minima                       (Eq. 9)
+//   k_refine   cross-check, 3x3 median and bilateral filling    (Eq. 10, Sec. III-E, Eq. 11)
 //   k_upscale  bilateral x / linear y upscale to full res      (Step8)
 #pragma once
 #include <hip/hip_runtime.h>
@@ -34,25 +34,41 @@ __device__ __forceinline__ int gray_of(const uint8_t* p) {
 }
 
 // ---------------------------------------------------------------- k_prep
-// One thread per half-res pixel of one image: the rounded-half-up mean of
-// the 3x3 gray block centred on (2x, 2y), borders clamped.
-// grid: (ceil(X/64), ceil(Y/4), 2 * npair), block (64, 4).
+// One workgroup = 64 x 8 half-res pixels of one image.  The gray values of
+// the full-res rows 2 y0 - 1 .. 2 y0 + 15 and columns 2 x0 - 1 .. 2 x0 + 128
+// (borders clamped) go to LDS; each thread then forms the rounded-half-up
+// mean of the 3x3 block centred on (2x, 2y) for two output rows.
+// grid: (ceil(X/64), ceil(Y/8), 2 * npair), block (64, 4).
+constexpr int kPrepRows = 8;
+
 __global__ void __launch_bounds__(256) k_prep(PairPtrs pp, int W, int H, int X, int Y,
                                               uint8_t* __restrict__ half) {
-  const int x = blockIdx.x * 64 + threadIdx.x;
-  const int y = blockIdx.y * 4 + threadIdx.y;
-  const int img = blockIdx.z;  // 2 * pair + (0 = left, 1 = right)
-  if (x >= X || y >= Y) return;
+  constexpr int TR = 2 * kPrepRows + 1, TC = 130;
+  __shared__ uint8_t g[TR][TC];
+  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kPrepRows, img = blockIdx.z;
   const int pair = img >> 1;
   const uint8_t* rgb = (img & 1) ? pp.right[pair] : pp.left[pair];
-  int s = 0;
-#pragma unroll
-  for (int j = -1; j <= 1; ++j) {
-    const uint8_t* row = rgb + (size_t)clampi(2 * y + j, 0, H - 1) * W * 3;
-#pragma unroll
-    for (int i = -1; i <= 1; ++i) s += gray_of(row + clampi(2 * x + i, 0, W - 1) * 3);
+  const int t = threadIdx.y * 64 + threadIdx.x;
+  for (int r = threadIdx.y; r < TR; r += 4) {
+    const uint8_t* row = rgb + (size_t)clampi(2 * y0 - 1 + r, 0, H - 1) * W * 3;
+    for (int c = threadIdx.x; c < TC; c += 64)
+      g[r][c] = (uint8_t)gray_of(row + (size_t)clampi(2 * x0 - 1 + c, 0, W - 1) * 3);
   }
-  half[(size_t)img * X * Y + (size_t)y * X + x] = (uint8_t)((s + 4) / 9);
+  (void)t;
+  __syncthreads();
+  const int lx = threadIdx.x, x = x0 + lx;
+  if (x >= X) return;
+#pragma unroll
+  for (int k = 0; k < 2; ++k) {
+    const int ly = threadIdx.y + 4 * k, y = y0 + ly;
+    if (y >= Y) break;
+    int s = 0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j)
+#pragma unroll
+      for (int i = 0; i < 3; ++i) s += g[2 * ly + j][2 * lx + i];
+    half[(size_t)img * X * Y + (size_t)y * X + x] = (uint8_t)((s + 4) / 9);
+  }
 }
 
 // ---------------------------------------------------------------- k_feat
@@ -64,59 +80,79 @@ constexpr uint32_t kSentinel = 1022u;
 constexpr int kFeatRows = 16;    // output rows per k_feat workgroup
 constexpr int kMaxArm = 127;
 
-// One workgroup = 64 columns x 16 rows of one image, 256 threads (64 x 4).
+// One workgroup = 64 columns x 16 rows of one image, one thread per pixel.
 // Two LDS tiles of the half image (borders clamped): rows y0-1..y0+16 over
 // the columns reachable by the horizontal arms and the census, and rows
 // y0-arm_y..y0+15+arm_y over the 64 columns for the vertical arms.
 //   census: 6 neighbours in three rows, bit k = [neighbour < centre]
 //   arms  : contiguous pixels with |I - I(centre)| < delta, capped per side
-//           and at the image border; packed m | n<<8 | M<<16 | N<<24
-// grid: (ceil(X/64), ceil(Y/16), 2 * npair), block (64, 4).
-__global__ void __launch_bounds__(256) k_feat(const uint8_t* __restrict__ half, int X, int Y,
-                                              int delta, int arm_x, int arm_y, int XP, int pad,
-                                              int XA, uint32_t* __restrict__ pk,
-                                              uint32_t* __restrict__ arms) {
+//           and at the image border; packed m | n<<8 | M<<16 | N<<24.
+//           Both sides of an axis grow together, one step per pixel
+//           distance, until no lane of the wave can grow any more.
+// grid: (ceil(X/64), ceil(Y/16), 2 * npair), block (64, 16).
+__global__ void __launch_bounds__(1024) k_feat(const uint8_t* __restrict__ half, int X, int Y,
+                                               int delta, int arm_x, int arm_y, int XP, int pad,
+                                               int XA, uint32_t* __restrict__ pk,
+                                               uint32_t* __restrict__ arms) {
   constexpr int TXW = 64 + 2 * (kMaxArm + 2);
   __shared__ uint8_t tx[kFeatRows + 2][TXW];
   __shared__ uint8_t ty[kFeatRows + 2 * kMaxArm][64];
   const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kFeatRows, img = blockIdx.z;
-  const int t = threadIdx.y * 64 + threadIdx.x;
   const uint8_t* h = half + (size_t)img * X * Y;
   const int hx = arm_x + 2, wx = 64 + 2 * hx;
-  for (int i = t; i < (kFeatRows + 2) * wx; i += 256) {
-    const int r = i / wx, c = i - r * wx;
-    tx[r][c] = h[(size_t)clampi(y0 - 1 + r, 0, Y - 1) * X + clampi(x0 - hx + c, 0, X - 1)];
+  for (int r = threadIdx.y; r < kFeatRows + 2; r += kFeatRows) {
+    const uint8_t* src = h + (size_t)clampi(y0 - 1 + r, 0, Y - 1) * X;
+    for (int c = threadIdx.x; c < wx; c += 64) tx[r][c] = src[clampi(x0 - hx + c, 0, X - 1)];
   }
   const int hy = kFeatRows + 2 * arm_y;
-  for (int i = t; i < hy * 64; i += 256) {
-    const int r = i >> 6, c = i & 63;
-    ty[r][c] = h[(size_t)clampi(y0 - arm_y + r, 0, Y - 1) * X + clampi(x0 + c, 0, X - 1)];
-  }
+  const int cx = clampi(x0 + (int)threadIdx.x, 0, X - 1);
+  for (int r = threadIdx.y; r < hy; r += kFeatRows)
+    ty[r][threadIdx.x] = h[(size_t)clampi(y0 - arm_y + r, 0, Y - 1) * X + cx];
   __syncthreads();
-  const int lx = threadIdx.x, x = x0 + lx;
-  if (x >= X) return;
-  for (int k = 0; k < kFeatRows / 4; ++k) {
-    const int ly = threadIdx.y + 4 * k, y = y0 + ly;
-    if (y >= Y) break;
-    const uint8_t* row = &tx[ly + 1][hx + lx];   // row[i] = I(x + i, y)
-    const int c = row[0];
-    int bits = 0;
-    bits |= (tx[ly][hx + lx - 1] < c) << 0;
-    bits |= (tx[ly][hx + lx + 1] < c) << 1;
-    bits |= (row[-2] < c) << 2;
-    bits |= (row[2] < c) << 3;
-    bits |= (tx[ly + 2][hx + lx - 1] < c) << 4;
-    bits |= (tx[ly + 2][hx + lx + 1] < c) << 5;
-    int m = 0, n = 0, M = 0, N = 0;
-    while (m < arm_x && x - m - 1 >= 0 && iabs(row[-m - 1] - c) < delta) ++m;
-    while (n < arm_x && x + n + 1 < X && iabs(row[n + 1] - c) < delta) ++n;
-    const int cy = ly + arm_y;                    // ty row of (x, y)
-    while (M < arm_y && y - M - 1 >= 0 && iabs(ty[cy - M - 1][lx] - c) < delta) ++M;
-    while (N < arm_y && y + N + 1 < Y && iabs(ty[cy + N + 1][lx] - c) < delta) ++N;
-    pk[((size_t)img * Y + y) * XP + pad + x] = (uint32_t)(2 * c) | ((uint32_t)bits << 16);
-    arms[((size_t)img * Y + y) * XA + x] =
-        (uint32_t)m | ((uint32_t)n << 8) | ((uint32_t)M << 16) | ((uint32_t)N << 24);
+  const int lx = threadIdx.x, ly = threadIdx.y, x = x0 + lx, y = y0 + ly;
+  if (x >= X || y >= Y) return;
+  const uint8_t* row = &tx[ly + 1][hx + lx];   // row[i] = I(x + i, y)
+  const int c = row[0];
+  int bits = 0;
+  bits |= (tx[ly][hx + lx - 1] < c) << 0;
+  bits |= (tx[ly][hx + lx + 1] < c) << 1;
+  bits |= (row[-2] < c) << 2;
+  bits |= (row[2] < c) << 3;
+  bits |= (tx[ly + 2][hx + lx - 1] < c) << 4;
+  bits |= (tx[ly + 2][hx + lx + 1] < c) << 5;
+  // horizontal arms: lanes stop at a dissimilar pixel or at their limit
+  int m = 0, n = 0;
+  {
+    const int lm = min(arm_x, x), ln = min(arm_x, X - 1 - x);
+    bool gm = lm > 0, gn = ln > 0;
+    for (int t = 1; t <= arm_x; ++t) {
+      if (__builtin_amdgcn_ballot_w64(gm || gn) == 0) break;
+      gm = gm && iabs(row[-t] - c) < delta;
+      gn = gn && iabs(row[t] - c) < delta;
+      m += gm;
+      n += gn;
+      gm = gm && t < lm;
+      gn = gn && t < ln;
+    }
   }
+  int M = 0, N = 0;
+  {
+    const uint8_t* col = &ty[ly + arm_y][lx];  // col[64 i] = I(x, y + i)
+    const int lM = min(arm_y, y), lN = min(arm_y, Y - 1 - y);
+    bool gM = lM > 0, gN = lN > 0;
+    for (int t = 1; t <= arm_y; ++t) {
+      if (__builtin_amdgcn_ballot_w64(gM || gN) == 0) break;
+      gM = gM && iabs(col[-64 * t] - c) < delta;
+      gN = gN && iabs(col[64 * t] - c) < delta;
+      M += gM;
+      N += gN;
+      gM = gM && t < lM;
+      gN = gN && t < lN;
+    }
+  }
+  pk[((size_t)img * Y + y) * XP + pad + x] = (uint32_t)(2 * c) | ((uint32_t)bits << 16);
+  arms[((size_t)img * Y + y) * XA + x] =
+      (uint32_t)m | ((uint32_t)n << 8) | ((uint32_t)M << 16) | ((uint32_t)N << 24);
 }
 
 // Fills the padded pk planes with kSentinel (run once when a plan is made;
@@ -152,8 +188,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uin
 }
 
 // cost table [census distance h][signed brightness difference + 512]: 7 rows
-// of 1024 entries; |difference| > 255 only arises against the sentinel
-constexpr int kTab = 7 * 1024;
+// of 1024 entries, row pitch 1026 so that equal differences in different rows
+// fall in different LDS banks; |difference| > 255 only arises against the
+// sentinel
+constexpr int kTabPitch = 1026;
+constexpr int kTab = 7 * kTabPitch;
 
 // LDS rows of the k_match plane for NS sub-passes of 128 row-buffer columns.
 __host__ __device__ constexpr int plane_rows(int ns) {
@@ -163,12 +202,12 @@ __host__ __device__ constexpr int plane_rows(int ns) {
 struct MatchArgs {
   const uint32_t* pk;     // [2*npair][Y][XP]  padded: gray*2 | census << 16
   const uint32_t* arms;   // [2*npair][Y][XA]  zero past column X
-  const uint16_t* tab;    // [7][1024]
-  uint32_t* keys;         // [npair][nchunk][2][Y][X]  (min CA) << 8 | argmin d
-  int X, Y, XP, pad, XA, arm_x, arm_y;
+  const uint16_t* tab;    // [7][kTabPitch]
+  uint32_t* keys;         // [npair][nchunk][2][nk]  (min CA) << 8 | argmin d
+  int X, Y, XP, pad, XA, nk, arm_x, arm_y;
   int nbands, nchunk, dlo, dhi;
   uint32_t pk_bytes, arms_bytes;  // sizes of the pk and arms buffers
-  // debug planes (pair 0, the single disparity dlo; NULL in the fast path)
+  // debug planes (pair 0, the single disparity dlo; used by the DBG variant)
   uint16_t* dbg_cost;
   uint32_t* dbg_cax;
   uint32_t* dbg_ca;
@@ -191,7 +230,7 @@ struct MatchArgs {
 // window sum below 2^24, hence exact.  KMAX (<= kKMax) bounds the output rows
 // per thread: a band has at most 16 * KMAX output rows.
 // grid: (nstrips, nbands * nchunk, 2 * npair), block 1024.
-template <int NS, int KMAX>
+template <int NS, int KMAX, bool DBG>
 __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   constexpr int PR = plane_rows(NS);
   __shared__ uint16_t s_tab[kTab];
@@ -213,12 +252,12 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   const int d0 = a.dlo + (chunk * span) / a.nchunk, d1 = a.dlo + ((chunk + 1) * span) / a.nchunk;
   const int hx = (a.arm_x + 2) & ~1;   // row buffer starts at column x0 - hx (even)
   const int sgn = base ? 1 : -1;       // other-image column is x + sgn * d
-  const size_t plane = (size_t)X * Y;
   const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(a.pk, a.pk_bytes);
   const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(a.arms, a.arms_bytes);
   const uint32_t img_b = (uint32_t)(2 * pair + base), img_o = (uint32_t)(2 * pair + (base ^ 1));
   const uint32_t pkrow = (uint32_t)a.XP * 4u, armrow = (uint32_t)a.XA * 4u;
-  const bool dbg = a.dbg_cost != nullptr && pair == 0 && base == a.dbg_base;
+  const bool dbg = DBG && pair == 0 && base == a.dbg_base;
+  (void)dbg;
 
   for (int i = t; i < kTab; i += kThreads) s_tab[i] = a.tab[i];
   if (t < 64) s_plane[t] = 0u;
@@ -248,33 +287,42 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   const uint32_t vb = (uint32_t)(a.pad + x0 - hx + 2 * lane) * 4u;
   __syncthreads();
 
+  const char* tb = reinterpret_cast<const char*>(s_tab) + 1024;
+  // cost of one pixel pair: byte offset of entry (h, 512 + diff) is
+  // h * 2 * kTabPitch + 2 * diff + 1024, and the stored grays are doubled
+  auto cost = [&](uint32_t b, uint32_t o) -> uint32_t {
+    const int e = (int)__builtin_popcount((b ^ o) >> 16) * (2 * kTabPitch) +
+                  ((int)(b & 0xffffu) - (int)(o & 0xffffu));
+    return *reinterpret_cast<const uint16_t*>(tb + e);
+  };
+  const uint32_t vx = (uint32_t)x * 4u;
+
   for (int d = d0; d < d1; ++d) {
     const uint32_t vo = vb + (uint32_t)(sgn * d * 4);
-    // ---- row pass
-    for (int r = wave; r < nb; r += kWaves) {
+    // ---- row pass: rows r = wave + 16 i; the loads of the next row are in
+    // flight while a row is computed
+    struct RowIn { u32x2 b[NS], o[NS]; uint32_t am; };
+    auto load_row = [&](int r, RowIn& in) {
       const uint32_t y = (uint32_t)(ya + r);
       const uint32_t sb = (img_b * (uint32_t)Y + y) * pkrow;
       const uint32_t so = (img_o * (uint32_t)Y + y) * pkrow;
-      const uint32_t am = __builtin_amdgcn_raw_buffer_load_b32(
-          ra, (uint32_t)x * 4u, (img_b * (uint32_t)Y + y) * armrow, 0);
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        in.b[s] = __builtin_amdgcn_raw_buffer_load_b64(rb, vb + s * 512, sb, 0);
+        in.o[s] = __builtin_amdgcn_raw_buffer_load_b64(rb, vo + s * 512, so, 0);
+      }
+      in.am = __builtin_amdgcn_raw_buffer_load_b32(ra, vx, (img_b * (uint32_t)Y + y) * armrow, 0);
+    };
+    auto do_row = [&](int r, const RowIn& in) {
+      const int y = ya + r;
       uint32_t carry = 0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const u32x2 bv = __builtin_amdgcn_raw_buffer_load_b64(rb, vb + s * 512, sb, 0);
-        const u32x2 ov = __builtin_amdgcn_raw_buffer_load_b64(rb, vo + s * 512, so, 0);
-        // byte offset of entry (h, 512 + diff): h * 2048 + 2 * diff + 1024, and the
-        // stored grays are already doubled
-        const int e0 = ((int)__builtin_popcount((bv.x ^ ov.x) >> 16) << 11) +
-                       ((int)(bv.x & 0xffffu) - (int)(ov.x & 0xffffu));
-        const int e1 = ((int)__builtin_popcount((bv.y ^ ov.y) >> 16) << 11) +
-                       ((int)(bv.y & 0xffffu) - (int)(ov.y & 0xffffu));
-        const char* tb = reinterpret_cast<const char*>(s_tab) + 1024;
-        const uint32_t c0 = *reinterpret_cast<const uint16_t*>(tb + e0);
-        const uint32_t c1 = *reinterpret_cast<const uint16_t*>(tb + e1);
+        const uint32_t c0 = cost(in.b[s].x, in.o[s].x), c1 = cost(in.b[s].y, in.o[s].y);
         const uint32_t p1 = wave_scan_incl(c0 + c1) + carry;
         if (NS > 1) carry = __builtin_amdgcn_readlane(p1, 63);
         *reinterpret_cast<u32x2*>(&s_row[wave][s * 128 + 2 * lane]) = u32x2{p1 - c1, p1};
-        if (dbg && d == a.dlo && (int)y >= y0 && (int)y < y1) {
+        if (DBG && dbg && d == a.dlo && y >= y0 && y < y1) {
           const int xc = x0 - hx + s * 128 + 2 * lane;
           if (xc >= x0 && xc < x0 + kTX && xc < X) a.dbg_cost[(size_t)y * X + xc] = (uint16_t)c0;
           if (xc + 1 >= x0 && xc + 1 < x0 + kTX && xc + 1 < X)
@@ -282,12 +330,22 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
         }
       }
       WAVE_LDS_ORDER();
-      const int m = am & 255u, n = (am >> 8) & 255u;
+      const int m = in.am & 255u, n = (in.am >> 8) & 255u;
       const uint32_t cax = s_row[wave][lane + hx + n] - s_row[wave][lane + hx - m - 1];
-      if (dbg && d == a.dlo && x < X && (int)y >= y0 && (int)y < y1)
-        a.dbg_cax[(size_t)y * X + x] = cax;
+      if (DBG && dbg && d == a.dlo && x < X && y >= y0 && y < y1) a.dbg_cax[(size_t)y * X + x] = cax;
       s_plane[(r + 1) * 64 + lane] = cax;
       WAVE_LDS_ORDER();
+    };
+    RowIn ra_in, rb_in;
+    if (wave < nb) load_row(wave, ra_in);
+    for (int r = wave; r < nb; r += 2 * kWaves) {
+      const bool has_b = r + kWaves < nb;
+      if (has_b) load_row(r + kWaves, rb_in);
+      do_row(r, ra_in);
+      if (has_b) {
+        if (r + 2 * kWaves < nb) load_row(r + 2 * kWaves, ra_in);
+        do_row(r + kWaves, rb_in);
+      }
     }
     __syncthreads();
     // ---- column pass: segment sums, segment offsets, prefix in place
@@ -297,7 +355,11 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
     s_seg[wave][c] = acc;
     __syncthreads();
     uint32_t off = 0;
-    for (int s = 0; s < wave; ++s) off += s_seg[s][c];
+#pragma unroll
+    for (int s = 0; s < kWaves; ++s) {
+      const uint32_t v = s_seg[s][c];
+      off += s < wave ? v : 0u;
+    }
 #pragma unroll 8
     for (int r = r0; r < r1; ++r) {
       off += s_plane[(r + 1) * 64 + c];
@@ -327,64 +389,57 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   int nout = o1 - o0 - wave;  // output rows left for this wave, from row k = 0
   __asm__ volatile("" : "+v"(nout));  // recompute the row tests here
   if (x < X) {
-    uint32_t* out = a.keys + ((size_t)(pair * a.nchunk + chunk) * 2 + base) * plane;
+    uint32_t* out = a.keys + ((size_t)(pair * a.nchunk + chunk) * 2 + base) * a.nk;
 #pragma unroll
     for (int k = 0; k < KMAX; ++k) {
       const int r = o0 + wave + k * kWaves;
       if (k * kWaves < nout) {
         out[(size_t)(ya + r) * X + x] = key[k];
         // a debug run covers the single disparity dlo, so the key holds CA
-        if (dbg) a.dbg_ca[(size_t)(ya + r) * X + x] = key[k] >> 8;
+        if (DBG && dbg) a.dbg_ca[(size_t)(ya + r) * X + x] = key[k] >> 8;
       }
     }
   }
 }
 
-// -------------------------------------------------------------- k_wta_cc
-// One workgroup per half-res row: min over the d-chunk keys gives D^L, D^R
-// (and the minimum aggregates when mincost != NULL); then the cross-check
-// GCP = [x - k >= 0 and D^R(x - k) = k], k = D^L(x)  (Eq. 10).
-// grid: (Y, npair), block 256.
-__global__ void __launch_bounds__(256) k_wta_cc(const uint32_t* __restrict__ keys, int nchunk,
-                                                int X, int Y, int16_t* __restrict__ disp,
-                                                uint32_t* __restrict__ mincost,
-                                                uint8_t* __restrict__ gcp) {
-  __shared__ int16_t s_dr[4096];
-  __shared__ int16_t s_dl[4096];
-  const int y = blockIdx.x, pair = blockIdx.y;
-  const size_t plane = (size_t)X * Y;
-  const uint32_t* kp = keys + (size_t)pair * nchunk * 2 * plane;
-  for (int x = threadIdx.x; x < X; x += 256) {
-    uint32_t kl = 0xffffffffu, kr = 0xffffffffu;
-    for (int c = 0; c < nchunk; ++c) {
-      const uint32_t vl = kp[((size_t)c * 2 + 0) * plane + (size_t)y * X + x];
-      const uint32_t vr = kp[((size_t)c * 2 + 1) * plane + (size_t)y * X + x];
-      kl = vl < kl ? vl : kl;
-      kr = vr < kr ? vr : kr;
+// ----------------------------------------------------------------- k_wta
+// Minimum key over the d-chunks for both bases: D = key & 255 (Eq. 9; the
+// key order makes the smallest d win ties), and the minimum aggregate
+// key >> 8 when mincost != NULL.  Four pixels per thread; planes have the
+// padded stride nk (a multiple of 64 pixels).
+// grid: (ceil(nk / 1024), npair), block 256.
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef int16_t i16x4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_wta(const uint32_t* __restrict__ keys, int nchunk,
+                                             int nk, int16_t* __restrict__ disp,
+                                             uint32_t* __restrict__ mincost) {
+  const int i = (blockIdx.x * 256 + threadIdx.x) * 4;
+  const int pair = blockIdx.y;
+  if (i >= nk) return;
+  const uint32_t* kp = keys + (size_t)pair * nchunk * 2 * nk + i;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    u32x4 m = *reinterpret_cast<const u32x4*>(kp + (size_t)b * nk);
+    for (int c = 1; c < nchunk; ++c) {
+      const u32x4 v = *reinterpret_cast<const u32x4*>(kp + ((size_t)c * 2 + b) * nk);
+      m.x = min(m.x, v.x); m.y = min(m.y, v.y); m.z = min(m.z, v.z); m.w = min(m.w, v.w);
     }
-    const size_t o = (size_t)y * X + x;
-    s_dl[x] = (int16_t)(kl & 255u);
-    s_dr[x] = (int16_t)(kr & 255u);
-    disp[(size_t)(2 * pair) * plane + o] = (int16_t)(kl & 255u);
-    disp[(size_t)(2 * pair + 1) * plane + o] = (int16_t)(kr & 255u);
-    if (mincost) {
-      mincost[(size_t)(2 * pair) * plane + o] = kl >> 8;
-      mincost[(size_t)(2 * pair + 1) * plane + o] = kr >> 8;
-    }
-  }
-  __syncthreads();
-  for (int x = threadIdx.x; x < X; x += 256) {
-    const int k = s_dl[x];
-    gcp[(size_t)pair * plane + (size_t)y * X + x] = (uint8_t)(x - k >= 0 && s_dr[x - k] == k);
+    const size_t o = (size_t)(2 * pair + b) * nk + i;
+    *reinterpret_cast<i16x4*>(disp + o) =
+        i16x4{(int16_t)(m.x & 255u), (int16_t)(m.y & 255u), (int16_t)(m.z & 255u),
+              (int16_t)(m.w & 255u)};
+    if (mincost) *reinterpret_cast<u32x4*>(mincost + o) = u32x4{m.x >> 8, m.y >> 8, m.z >> 8, m.w >> 8};
   }
 }
 
 // -------------------------------------------------------------- k_refine
-// One workgroup per half-res row: M = 3x3 median of D^L (borders clamped);
-// GCPs keep M; a non-GCP takes the nearest GCPs left (x-i) and right (x+j):
-// linear interpolation from M(x-i) toward M(x+j), rounded half up, when they
-// differ by at most T, else the side of strictly closer brightness (the right
-// one on a tie) (Sec. III-E).  One side only: copy it; none: 0.
+// One workgroup per half-res row.  GCP(x) = [x - k >= 0 and D^R(x - k) = k],
+// k = D^L(x) (Eq. 10); M = 3x3 median of D^L (borders clamped); GCPs keep M;
+// a non-GCP takes the nearest GCPs left (x-i) and right (x+j): linear
+// interpolation from M(x-i) toward M(x+j), rounded half up, when they differ
+// by at most T, else the side of strictly closer brightness (the right one on
+// a tie) (Sec. III-E).  One side only: copy it; none: 0.
 // grid: (Y, npair), block 256.
 __device__ __forceinline__ int floor_div_pos(int n, int d) {  // d > 0
   return n >= 0 ? n / d : -((-n + d - 1) / d);
@@ -401,10 +456,11 @@ __device__ __forceinline__ int median9(int* v) {
   return v[4];
 }
 
-__global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp,
-                                                const uint8_t* __restrict__ gcp,
+__global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp, int nk,
                                                 const uint32_t* __restrict__ pk, int XP, int pad,
-                                                int X, int Y, int T, int16_t* __restrict__ med_out,
+                                                int X, int Y, int T,
+                                                uint8_t* __restrict__ gcp_out,
+                                                int16_t* __restrict__ med_out,
                                                 int16_t* __restrict__ filled) {
   __shared__ int16_t s_med[4096];
   __shared__ uint8_t s_g[4096];
@@ -414,17 +470,21 @@ __global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp
   __shared__ int s_firstg[256];
   const int y = blockIdx.x, pair = blockIdx.y, t = threadIdx.x;
   const size_t plane = (size_t)X * Y;
-  const int16_t* dl = disp + (size_t)(2 * pair) * plane;
+  const int16_t* dl = disp + (size_t)(2 * pair) * nk;
+  const int16_t* dr = disp + (size_t)(2 * pair + 1) * nk + (size_t)y * X;
   const int ym = max(y - 1, 0), yp = min(y + 1, Y - 1);
   for (int x = t; x < X; x += 256) {
     const int xm = max(x - 1, 0), xp = min(x + 1, X - 1);
     int v[9] = {dl[(size_t)ym * X + xm], dl[(size_t)ym * X + x], dl[(size_t)ym * X + xp],
                 dl[(size_t)y * X + xm],  dl[(size_t)y * X + x],  dl[(size_t)y * X + xp],
                 dl[(size_t)yp * X + xm], dl[(size_t)yp * X + x], dl[(size_t)yp * X + xp]};
+    const int k = v[4];
+    const uint8_t g = (uint8_t)(x - k >= 0 && dr[x - k] == k);
+    s_g[x] = g;
+    if (gcp_out) gcp_out[(size_t)pair * plane + (size_t)y * X + x] = g;
     const int m = median9(v);
     s_med[x] = (int16_t)m;
     if (med_out) med_out[(size_t)pair * plane + (size_t)y * X + x] = (int16_t)m;
-    s_g[x] = gcp[(size_t)pair * plane + (size_t)y * X + x];
     s_h[x] = (uint8_t)((pk[((size_t)(2 * pair) * Y + y) * XP + pad + x] & 1023u) >> 1);
   }
   __syncthreads();
@@ -480,19 +540,14 @@ __global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp
 }
 
 // ------------------------------------------------------------- k_upscale
-// One thread per full-res output pixel (Step8).  Along x: even columns take
-// 2 D+(x); an odd column between D+(x) and D+(x+1) takes their sum (the
-// doubled midpoint) when they differ by at most T, else the doubled value of
-// the side whose full-res gray is strictly closer (the right one on a tie);
-// a last odd column copies.  Along y: odd rows are the rounded-up mean of
-// the two neighbouring upscaled rows; a last odd row copies.
-// grid: (ceil(W/64), ceil(H/4), npair), block (64, 4).
-__device__ __forceinline__ int up_x(const int16_t* frow, const uint8_t* rgb_row, int xo, int X,
-                                    int T) {
-  const int x = xo >> 1;
-  const int dlv = frow[x];
-  if ((xo & 1) == 0 || x + 1 >= X) return 2 * dlv;
-  const int drv = frow[x + 1];
+// One thread per 2x2 block of full-res output pixels (Step8).  Along x: even
+// columns take 2 D+(x); an odd column between D+(x) and D+(x+1) takes their
+// sum (the doubled midpoint) when they differ by at most T, else the doubled
+// value of the side whose full-res gray is strictly closer (the right one on
+// a tie); a last odd column copies.  Along y: odd rows are the rounded-up
+// mean of the two neighbouring upscaled rows; a last odd row copies.
+// grid: (ceil(X/64), ceil(Y/4), npair), block (64, 4).
+__device__ __forceinline__ int up_odd(int dlv, int drv, const uint8_t* rgb_row, int xo, int T) {
   if (iabs(dlv - drv) <= T) return dlv + drv;
   const int g0 = gray_of(rgb_row + (xo - 1) * 3), g1 = gray_of(rgb_row + xo * 3),
             g2 = gray_of(rgb_row + (xo + 1) * 3);
@@ -501,19 +556,34 @@ __device__ __forceinline__ int up_x(const int16_t* frow, const uint8_t* rgb_row,
 
 __global__ void __launch_bounds__(256) k_upscale(PairPtrs pp, const int16_t* __restrict__ filled,
                                                  int W, int H, int X, int Y, int T) {
-  const int xo = blockIdx.x * 64 + threadIdx.x;
-  const int yo = blockIdx.y * 4 + threadIdx.y;
+  const int x = blockIdx.x * 64 + threadIdx.x;
+  const int y = blockIdx.y * 4 + threadIdx.y;
   const int pair = blockIdx.z;
-  if (xo >= W || yo >= H) return;
+  if (x >= X || y >= Y) return;
   const int16_t* f = filled + (size_t)pair * X * Y;
   const uint8_t* rgb = pp.left[pair];
-  const int y = yo >> 1;
-  int v = up_x(f + (size_t)y * X, rgb + (size_t)(2 * y) * W * 3, xo, X, T);
-  if ((yo & 1) && y + 1 < Y) {
-    const int v2 = up_x(f + (size_t)(y + 1) * X, rgb + (size_t)(2 * y + 2) * W * 3, xo, X, T);
-    v = (v + v2 + 1) >> 1;
+  int16_t* out = pp.out[pair];
+  const int xo = 2 * x, yo = 2 * y;
+  const bool hasr = x + 1 < X, hasd = y + 1 < Y;
+  const int a = f[(size_t)y * X + x], b = hasr ? f[(size_t)y * X + x + 1] : a;
+  // upscaled row y at columns 2x and 2x+1
+  const int u0 = 2 * a;
+  const int u1 = hasr ? up_odd(a, b, rgb + (size_t)yo * W * 3, xo + 1, T) : 2 * a;
+  const bool odd_col = xo + 1 < W;
+  out[(size_t)yo * W + xo] = (int16_t)u0;
+  if (odd_col) out[(size_t)yo * W + xo + 1] = (int16_t)u1;
+  if (yo + 1 < H) {
+    int v0 = u0, v1 = u1;
+    if (hasd) {
+      const int c = f[(size_t)(y + 1) * X + x], e = hasr ? f[(size_t)(y + 1) * X + x + 1] : c;
+      const int w0 = 2 * c;
+      const int w1 = hasr ? up_odd(c, e, rgb + (size_t)(yo + 2) * W * 3, xo + 1, T) : 2 * c;
+      v0 = (u0 + w0 + 1) >> 1;
+      v1 = (u1 + w1 + 1) >> 1;
+    }
+    out[(size_t)(yo + 1) * W + xo] = (int16_t)v0;
+    if (odd_col) out[(size_t)(yo + 1) * W + xo + 1] = (int16_t)v1;
   }
-  pp.out[pair][(size_t)yo * W + xo] = (int16_t)v;
 }
 
 }  // namespace stereo_dev

@@ -34,6 +34,7 @@ struct Plan {
   int cmax = 0;
   int ns = 1, kmax = 8, nstrips = 0, nbands = 0, nchunk = 0;
   int XP = 0, pad = 0, XA = 0;  // padded pitches of pk and arms
+  int nk = 0;                   // padded plane stride of keys, disp and mincost
   size_t bytes = 0;
   // device memory, one block carved into planes
   void* block = nullptr;
@@ -181,9 +182,11 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
   const size_t n = (size_t)pl->X * pl->Y;
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t npk = (size_t)2 * npair * pl->Y * pl->XP, nar = (size_t)2 * npair * pl->Y * pl->XA;
+  pl->nk = (int)((n + 63) & ~size_t(63));
+  const size_t nk = pl->nk;
   size_t bytes = al(2 * npair * n) + al(npk * 4) + al(nar * 4) + al(kTab * 2) +
-                 al((size_t)npair * pl->nchunk * 2 * n * 4) + al(2 * npair * n * 2) +
-                 al(2 * npair * n * 4) + al(npair * n) + al(npair * n * 2) + al(npair * n * 2);
+                 al((size_t)npair * pl->nchunk * 2 * nk * 4) + al(2 * npair * nk * 2) +
+                 al(2 * npair * nk * 4) + al(npair * n) + al(npair * n * 2) + al(npair * n * 2);
   if (c->mem_cap && c->used + bytes > c->mem_cap) {
     delete pl;
     return fail(c, STEREO_ENOMEM, "plan needs %zu bytes, cap %zu, in use %zu", bytes, c->mem_cap,
@@ -201,19 +204,20 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
   pl->pk = carve<uint32_t>(cur, npk);
   pl->arms = carve<uint32_t>(cur, nar);
   pl->tab = carve<uint16_t>(cur, kTab);
-  pl->keys = carve<uint32_t>(cur, (size_t)npair * pl->nchunk * 2 * n);
-  pl->disp = carve<int16_t>(cur, 2 * npair * n);
-  pl->mincost = carve<uint32_t>(cur, 2 * npair * n);
+  pl->keys = carve<uint32_t>(cur, (size_t)npair * pl->nchunk * 2 * nk);
+  pl->disp = carve<int16_t>(cur, 2 * npair * nk);
+  pl->mincost = carve<uint32_t>(cur, 2 * npair * nk);
   pl->gcp = carve<uint8_t>(cur, npair * n);
   pl->med = carve<int16_t>(cur, npair * n);
   pl->filled = carve<int16_t>(cur, npair * n);
   // table [census distance h][512 + signed brightness difference]: differences
   // beyond +-255 only arise against the padding sentinel and cost C_max
   static uint16_t tab[kTab];
+  std::memset(tab, 0, sizeof tab);
   for (int hd = 0; hd < 7; ++hd)
     for (int i = 0; i < 1024; ++i) {
       const int a = i < 512 ? 512 - i : i - 512;
-      tab[hd * 1024 + i] = (uint16_t)(a < 256 ? pl->lut_ad[a] + pl->lut_mc[hd] : pl->cmax);
+      tab[hd * kTabPitch + i] = (uint16_t)(a < 256 ? pl->lut_ad[a] + pl->lut_mc[hd] : pl->cmax);
     }
   e = hipMemcpy(pl->tab, tab, sizeof tab, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(pl->arms, 0, nar * 4);
@@ -263,7 +267,7 @@ int get_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int 
 MatchArgs match_args(const Plan& pl, int dlo, int dhi, int nchunk) {
   MatchArgs a{};
   a.pk = pl.pk; a.arms = pl.arms; a.tab = pl.tab; a.keys = pl.keys;
-  a.X = pl.X; a.Y = pl.Y; a.XP = pl.XP; a.pad = pl.pad; a.XA = pl.XA;
+  a.X = pl.X; a.Y = pl.Y; a.XP = pl.XP; a.pad = pl.pad; a.XA = pl.XA; a.nk = pl.nk;
   a.arm_x = pl.p.arm_x; a.arm_y = pl.p.arm_y;
   a.pk_bytes = (uint32_t)((size_t)2 * pl.npair * pl.Y * pl.XP * 4);
   a.arms_bytes = (uint32_t)((size_t)2 * pl.npair * pl.Y * pl.XA * 4);
@@ -271,23 +275,24 @@ MatchArgs match_args(const Plan& pl, int dlo, int dhi, int nchunk) {
   return a;
 }
 
-template <int NSUB>
+template <int NS, bool DBG>
 void launch_match_k(const Plan& pl, const MatchArgs& a, dim3 grid, hipStream_t s) {
   switch (pl.kmax) {
-    case 8: hipLaunchKernelGGL((k_match<NSUB, 8>), grid, dim3(kThreads), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_match<NSUB, 16>), grid, dim3(kThreads), 0, s, a); break;
-    case 24: hipLaunchKernelGGL((k_match<NSUB, 24>), grid, dim3(kThreads), 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_match<NSUB, 32>), grid, dim3(kThreads), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_match<NSUB, kKMax>), grid, dim3(kThreads), 0, s, a); break;
+    case 8: hipLaunchKernelGGL((k_match<NS, 8, DBG>), grid, dim3(kThreads), 0, s, a); break;
+    case 16: hipLaunchKernelGGL((k_match<NS, 16, DBG>), grid, dim3(kThreads), 0, s, a); break;
+    case 24: hipLaunchKernelGGL((k_match<NS, 24, DBG>), grid, dim3(kThreads), 0, s, a); break;
+    case 32: hipLaunchKernelGGL((k_match<NS, 32, DBG>), grid, dim3(kThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_match<NS, kKMax, DBG>), grid, dim3(kThreads), 0, s, a); break;
   }
 }
 
 void launch_match(const Plan& pl, const MatchArgs& a, int npair, hipStream_t s) {
   dim3 grid(pl.nstrips, pl.nbands * a.nchunk, 2 * npair);
+  const bool dbg = a.dbg_cost != nullptr;
   switch (pl.ns) {
-    case 1: launch_match_k<1>(pl, a, grid, s); break;
-    case 2: launch_match_k<2>(pl, a, grid, s); break;
-    default: launch_match_k<3>(pl, a, grid, s); break;
+    case 1: dbg ? launch_match_k<1, true>(pl, a, grid, s) : launch_match_k<1, false>(pl, a, grid, s); break;
+    case 2: dbg ? launch_match_k<2, true>(pl, a, grid, s) : launch_match_k<2, false>(pl, a, grid, s); break;
+    default: dbg ? launch_match_k<3, true>(pl, a, grid, s) : launch_match_k<3, false>(pl, a, grid, s); break;
   }
 }
 
@@ -315,23 +320,25 @@ int run(stereo_ctx* c, Plan& pl, const PairPtrs& pp, int npair, bool keep, bool 
   auto mark = [&](int i) { if (ev) (void)hipEventRecord(ev[i], s); };
   dim3 b2(64, 4);
   mark(0);
-  hipLaunchKernelGGL(k_prep, dim3((X + 63) / 64, (Y + 3) / 4, 2 * npair), b2, 0, s, pp, pl.W,
-                     pl.H, X, Y, pl.half);
+  hipLaunchKernelGGL(k_prep, dim3((X + 63) / 64, (Y + kPrepRows - 1) / kPrepRows, 2 * npair), b2,
+                     0, s, pp, pl.W, pl.H, X, Y, pl.half);
   mark(1);
-  hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + kFeatRows - 1) / kFeatRows, 2 * npair), b2, 0,
+  hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + kFeatRows - 1) / kFeatRows, 2 * npair),
+                     dim3(64, kFeatRows), 0,
                      s, pl.half, X, Y, pl.p.color_delta, pl.p.arm_x, pl.p.arm_y, pl.XP, pl.pad,
                      pl.XA, pl.pk, pl.arms);
   mark(2);
   launch_match(pl, match_args(pl, 0, pl.D, pl.nchunk), npair, s);
   mark(3);
-  hipLaunchKernelGGL(k_wta_cc, dim3(Y, npair), dim3(256), 0, s, pl.keys, pl.nchunk, X, Y, pl.disp,
-                     keep ? pl.mincost : nullptr, pl.gcp);
+  hipLaunchKernelGGL(k_wta, dim3((pl.nk + 1023) / 1024, npair), dim3(256), 0, s, pl.keys,
+                     pl.nchunk, pl.nk, pl.disp, keep ? pl.mincost : nullptr);
   mark(4);
-  hipLaunchKernelGGL(k_refine, dim3(Y, npair), dim3(256), 0, s, pl.disp, pl.gcp, pl.pk, pl.XP,
-                     pl.pad, X, Y, pl.p.fill_T, keep ? pl.med : nullptr, pl.filled);
+  hipLaunchKernelGGL(k_refine, dim3(Y, npair), dim3(256), 0, s, pl.disp, pl.nk, pl.pk, pl.XP,
+                     pl.pad, X, Y, pl.p.fill_T, keep ? pl.gcp : nullptr, keep ? pl.med : nullptr,
+                     pl.filled);
   mark(5);
-  hipLaunchKernelGGL(k_upscale, dim3((pl.W + 63) / 64, (pl.H + 3) / 4, npair), b2, 0, s, pp,
-                     pl.filled, pl.W, pl.H, X, Y, pl.p.fill_T);
+  hipLaunchKernelGGL(k_upscale, dim3((X + 63) / 64, (Y + 3) / 4, npair), b2, 0, s, pp, pl.filled,
+                     pl.W, pl.H, X, Y, pl.p.fill_T);
   mark(6);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(c, STEREO_EHIP, "kernel launch: %s", hipGetErrorString(e));
@@ -536,14 +543,14 @@ int stereo_get_intermediate(stereo_ctx* c, int which, int d, void* dst, size_t b
     case STEREO_I_MINCOST_L: case STEREO_I_MINCOST_R: {
       if (!need(4 * n)) break;
       HIP_TRY(c, hipStreamSynchronize(stream));
-      HIP_TRY(c, hipMemcpy(dst, pl->mincost + (which == STEREO_I_MINCOST_R ? n : 0), 4 * n,
+      HIP_TRY(c, hipMemcpy(dst, pl->mincost + (which == STEREO_I_MINCOST_R ? pl->nk : 0), 4 * n,
                            hipMemcpyDeviceToHost));
       return 0;
     }
     case STEREO_I_DISP_L: case STEREO_I_DISP_R: {
       if (!need(2 * n)) break;
       HIP_TRY(c, hipStreamSynchronize(stream));
-      HIP_TRY(c, hipMemcpy(dst, pl->disp + (which == STEREO_I_DISP_R ? n : 0), 2 * n,
+      HIP_TRY(c, hipMemcpy(dst, pl->disp + (which == STEREO_I_DISP_R ? pl->nk : 0), 2 * n,
                            hipMemcpyDeviceToHost));
       return 0;
     }
