@@ -44,7 +44,45 @@ def parse():
     ap.add_argument("--latency-frames", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run plain device copies of MIB MiB (reference for the "
+                         "FETCH_SIZE / WRITE_SIZE counters) and exit")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_match_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2212_00488_amd", "csrc", "kernels.hip.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_match launch from the committed counter summary, or
+    None when the kernel source has changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def calibrate_copy(mib: int):
+    import torch
+    n = mib * (1 << 20)
+    a = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty(n, dtype=torch.uint8, device="cuda:0")
+    a.fill_(1)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": n, "copies": 5}), flush=True)
 
 
 def percentile(v, q):
@@ -73,6 +111,9 @@ def cpu_baseline(pair, seconds):
 
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy(args.calibrate_copy)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
                           "(frames are independent, see the sharding notes)"}))
@@ -143,7 +184,7 @@ def main():
         "stages_ms": {k: round(v, 5) for k, v in stage_ms.items()},
         "roofline": {"kernel": "k_match", "bound": "alu", "achieved": round(achieved / 1e12, 3),
                      "peak": round(PEAK_INT_OPS / 1e12, 3), "unit": "Tops/s",
-                     "frac": round(achieved / PEAK_INT_OPS, 4), "traffic": None,
+                     "frac": round(achieved / PEAK_INT_OPS, 4), "traffic": measured_traffic(),
                      "ops_per_eval": OPS_PER_EVAL, "evals_per_launch": evals,
                      "avg_launch_ms": round(stage_ms["cost_aggregate_wta"], 5)},
     }

@@ -20,6 +20,7 @@ constexpr int kWaves = 16;        // k_match workgroup = 16 waves
 constexpr int kThreads = kWaves * 64;
 constexpr int kKMax = 34;         // most output rows per k_match thread (band <= 544 rows)
 constexpr int kLdsBytes = 163840; // LDS per workgroup on gfx950
+constexpr int kXcds = 8;          // accelerator complex dies, each with its own L2
 
 struct PairPtrs {
   const uint8_t* left[kMaxPairs];
@@ -77,19 +78,52 @@ __global__ void __launch_bounds__(256) k_prep(PairPtrs pp, int W, int H, int X, 
 // brightness difference to any pixel exceeds 255, so that the cost table
 // returns C_max there (the x - d < 0 / x + d >= X convention) without a branch.
 constexpr uint32_t kSentinel = 1022u;
-constexpr int kFeatRows = 16;    // output rows per k_feat workgroup
+constexpr int kFeatRows = 32;    // output rows per k_feat workgroup
 constexpr int kMaxArm = 127;
 
-// One workgroup = 64 columns x 16 rows of one image, one thread per pixel.
-// Two LDS tiles of the half image (borders clamped): rows y0-1..y0+16 over
+// Grows the two arms of one axis for one pixel of value c: p points at the
+// pixel in an LDS tile, stride is the tile distance of one pixel step.  A
+// side grows by one while the next pixel satisfies |I - c| < delta and the
+// side is below its limit lim_* = min(cap, distance to the border).  Four
+// steps are evaluated per round (their eight LDS reads issued together) and
+// the rounds end once no lane of the wave can grow.
+template <int STRIDE>
+__device__ __forceinline__ void grow_arms(const uint8_t* p, int c, int delta, int cap,
+                                          int lim_neg, int lim_pos, int& neg, int& pos) {
+  // |v - c| < delta  <=>  (unsigned)(v + k) < w
+  const int k = delta - 1 - c;
+  const unsigned w = 2u * (unsigned)delta - 1u;
+  bool gn = delta > 0 && lim_neg > 0, gp = delta > 0 && lim_pos > 0;
+  neg = 0;
+  pos = 0;
+  for (int t0 = 1; t0 <= cap; t0 += 4) {
+    if (__builtin_amdgcn_ballot_w64(gn || gp) == 0) break;
+    int vn[4], vp[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int tt = min(t0 + u, cap);
+      vn[u] = p[-tt * STRIDE];
+      vp[u] = p[tt * STRIDE];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int t = t0 + u;
+      gn = gn && t <= lim_neg && (unsigned)(vn[u] + k) < w;
+      gp = gp && t <= lim_pos && (unsigned)(vp[u] + k) < w;
+      neg += gn;
+      pos += gp;
+    }
+  }
+}
+
+// One workgroup = 64 columns x 32 rows of one image, two pixels per thread.
+// Two LDS tiles of the half image (borders clamped): rows y0-1..y0+32 over
 // the columns reachable by the horizontal arms and the census, and rows
-// y0-arm_y..y0+15+arm_y over the 64 columns for the vertical arms.
+// y0-arm_y..y0+31+arm_y over the 64 columns for the vertical arms.
 //   census: 6 neighbours in three rows, bit k = [neighbour < centre]
 //   arms  : contiguous pixels with |I - I(centre)| < delta, capped per side
-//           and at the image border; packed m | n<<8 | M<<16 | N<<24.
-//           Both sides of an axis grow together, one step per pixel
-//           distance, until no lane of the wave can grow any more.
-// grid: (ceil(X/64), ceil(Y/16), 2 * npair), block (64, 16).
+//           and at the image border; packed m | n<<8 | M<<16 | N<<24
+// grid: (ceil(X/64), ceil(Y/32), 2 * npair), block (64, 16).
 __global__ void __launch_bounds__(1024) k_feat(const uint8_t* __restrict__ half, int X, int Y,
                                                int delta, int arm_x, int arm_y, int XP, int pad,
                                                int XA, uint32_t* __restrict__ pk,
@@ -100,59 +134,36 @@ __global__ void __launch_bounds__(1024) k_feat(const uint8_t* __restrict__ half,
   const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kFeatRows, img = blockIdx.z;
   const uint8_t* h = half + (size_t)img * X * Y;
   const int hx = arm_x + 2, wx = 64 + 2 * hx;
-  for (int r = threadIdx.y; r < kFeatRows + 2; r += kFeatRows) {
+  for (int r = threadIdx.y; r < kFeatRows + 2; r += 16) {
     const uint8_t* src = h + (size_t)clampi(y0 - 1 + r, 0, Y - 1) * X;
     for (int c = threadIdx.x; c < wx; c += 64) tx[r][c] = src[clampi(x0 - hx + c, 0, X - 1)];
   }
   const int hy = kFeatRows + 2 * arm_y;
   const int cx = clampi(x0 + (int)threadIdx.x, 0, X - 1);
-  for (int r = threadIdx.y; r < hy; r += kFeatRows)
+  for (int r = threadIdx.y; r < hy; r += 16)
     ty[r][threadIdx.x] = h[(size_t)clampi(y0 - arm_y + r, 0, Y - 1) * X + cx];
   __syncthreads();
-  const int lx = threadIdx.x, ly = threadIdx.y, x = x0 + lx, y = y0 + ly;
-  if (x >= X || y >= Y) return;
-  const uint8_t* row = &tx[ly + 1][hx + lx];   // row[i] = I(x + i, y)
-  const int c = row[0];
-  int bits = 0;
-  bits |= (tx[ly][hx + lx - 1] < c) << 0;
-  bits |= (tx[ly][hx + lx + 1] < c) << 1;
-  bits |= (row[-2] < c) << 2;
-  bits |= (row[2] < c) << 3;
-  bits |= (tx[ly + 2][hx + lx - 1] < c) << 4;
-  bits |= (tx[ly + 2][hx + lx + 1] < c) << 5;
-  // horizontal arms: lanes stop at a dissimilar pixel or at their limit
-  int m = 0, n = 0;
-  {
-    const int lm = min(arm_x, x), ln = min(arm_x, X - 1 - x);
-    bool gm = lm > 0, gn = ln > 0;
-    for (int t = 1; t <= arm_x; ++t) {
-      if (__builtin_amdgcn_ballot_w64(gm || gn) == 0) break;
-      gm = gm && iabs(row[-t] - c) < delta;
-      gn = gn && iabs(row[t] - c) < delta;
-      m += gm;
-      n += gn;
-      gm = gm && t < lm;
-      gn = gn && t < ln;
-    }
+  const int lx = threadIdx.x, x = x0 + lx;
+  if (x >= X) return;
+  for (int q = 0; q < kFeatRows / 16; ++q) {
+    const int ly = threadIdx.y + 16 * q, y = y0 + ly;
+    if (y >= Y) break;
+    const uint8_t* row = &tx[ly + 1][hx + lx];   // row[i] = I(x + i, y)
+    const int c = row[0];
+    int bits = 0;
+    bits |= (tx[ly][hx + lx - 1] < c) << 0;
+    bits |= (tx[ly][hx + lx + 1] < c) << 1;
+    bits |= (row[-2] < c) << 2;
+    bits |= (row[2] < c) << 3;
+    bits |= (tx[ly + 2][hx + lx - 1] < c) << 4;
+    bits |= (tx[ly + 2][hx + lx + 1] < c) << 5;
+    int m, n, M, N;
+    grow_arms<1>(row, c, delta, arm_x, min(arm_x, x), min(arm_x, X - 1 - x), m, n);
+    grow_arms<64>(&ty[ly + arm_y][lx], c, delta, arm_y, min(arm_y, y), min(arm_y, Y - 1 - y), M, N);
+    pk[((size_t)img * Y + y) * XP + pad + x] = (uint32_t)(2 * c) | ((uint32_t)bits << 16);
+    arms[((size_t)img * Y + y) * XA + x] =
+        (uint32_t)m | ((uint32_t)n << 8) | ((uint32_t)M << 16) | ((uint32_t)N << 24);
   }
-  int M = 0, N = 0;
-  {
-    const uint8_t* col = &ty[ly + arm_y][lx];  // col[64 i] = I(x, y + i)
-    const int lM = min(arm_y, y), lN = min(arm_y, Y - 1 - y);
-    bool gM = lM > 0, gN = lN > 0;
-    for (int t = 1; t <= arm_y; ++t) {
-      if (__builtin_amdgcn_ballot_w64(gM || gN) == 0) break;
-      gM = gM && iabs(col[-64 * t] - c) < delta;
-      gN = gN && iabs(col[64 * t] - c) < delta;
-      M += gM;
-      N += gN;
-      gM = gM && t < lM;
-      gN = gN && t < lN;
-    }
-  }
-  pk[((size_t)img * Y + y) * XP + pad + x] = (uint32_t)(2 * c) | ((uint32_t)bits << 16);
-  arms[((size_t)img * Y + y) * XA + x] =
-      (uint32_t)m | ((uint32_t)n << 8) | ((uint32_t)M << 16) | ((uint32_t)N << 24);
 }
 
 // Fills the padded pk planes with kSentinel (run once when a plan is made;
@@ -206,6 +217,7 @@ struct MatchArgs {
   uint32_t* keys;         // [npair][nchunk][2][nk]  (min CA) << 8 | argmin d
   int X, Y, XP, pad, XA, nk, arm_x, arm_y;
   int nbands, nchunk, dlo, dhi;
+  int nstrips, ngroups;   // groups = strips x bands x 2 bases x pairs
   uint32_t pk_bytes, arms_bytes;  // sizes of the pk and arms buffers
   // debug planes (pair 0, the single disparity dlo; used by the DBG variant)
   uint16_t* dbg_cost;
@@ -229,7 +241,7 @@ struct MatchArgs {
 // of Eq. 6 term for term.  Sums wrap modulo 2^32; every difference taken is a
 // window sum below 2^24, hence exact.  KMAX (<= kKMax) bounds the output rows
 // per thread: a band has at most 16 * KMAX output rows.
-// grid: (nstrips, nbands * nchunk, 2 * npair), block 1024.
+// grid: ceil(groups / 8) * 8 * nchunk workgroups (1-D), block 1024.
 template <int NS, int KMAX, bool DBG>
 __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   constexpr int PR = plane_rows(NS);
@@ -241,9 +253,19 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: row offsets stay scalar
   const int X = a.X, Y = a.Y;
-  const int x0 = blockIdx.x * kTX;
-  const int band = blockIdx.y % a.nbands, chunk = blockIdx.y / a.nbands;
-  const int pair = blockIdx.z >> 1, base = blockIdx.z & 1;
+  // Workgroups are dealt to the 8 XCDs in turn (id mod 8).  All d-chunks of
+  // one (strip, band, base, pair) group read the same image rows, so they are
+  // given ids of one residue mod 8: the group's rows stay in one XCD's L2.
+  const int wg = blockIdx.x, xcd = wg & (kXcds - 1), j = wg / kXcds;
+  const int local = j / a.nchunk, chunk = j - local * a.nchunk;
+  int group = local * kXcds + xcd;
+  if (group >= a.ngroups) return;  // padding workgroup
+  const int strip = group % a.nstrips;
+  group /= a.nstrips;
+  const int band = group % a.nbands;
+  group /= a.nbands;
+  const int base = group & 1, pair = group >> 1;
+  const int x0 = strip * kTX;
   const int ob = (Y + a.nbands - 1) / a.nbands;
   const int y0 = band * ob, y1 = min(Y, y0 + ob);
   const int ya = max(0, y0 - a.arm_y), yb = min(Y, y1 + a.arm_y);
@@ -263,7 +285,9 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   if (t < 64) s_plane[t] = 0u;
 
   const int c = lane, x = x0 + lane;
-  const int seg_len = (nb + kWaves - 1) / kWaves;
+  // rows of the band in segments of an even length, one per wave (the row
+  // pass takes its rows in pairs)
+  const int seg_len = 2 * ((nb + 2 * kWaves - 1) / (2 * kWaves));
   const int r0 = min(wave * seg_len, nb), r1 = min(r0 + seg_len, nb);
 
   // Output rows of this thread: r = o0 + wave + 16 k.  marm[k / 2] packs the
@@ -299,8 +323,10 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
 
   for (int d = d0; d < d1; ++d) {
     const uint32_t vo = vb + (uint32_t)(sgn * d * 4);
-    // ---- row pass: rows r = wave + 16 i; the loads of the next row are in
-    // flight while a row is computed
+    // ---- row pass over this wave's rows r0..r1-1, two rows at a time (their
+    // lookups and scans interleave), the loads of the next two rows in flight.
+    // CA_x of a row is added to a running column sum, so the plane receives
+    // the column prefix within the wave's segment of rows.
     struct RowIn { u32x2 b[NS], o[NS]; uint32_t am; };
     auto load_row = [&](int r, RowIn& in) {
       const uint32_t y = (uint32_t)(ya + r);
@@ -313,57 +339,86 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
       }
       in.am = __builtin_amdgcn_raw_buffer_load_b32(ra, vx, (img_b * (uint32_t)Y + y) * armrow, 0);
     };
-    auto do_row = [&](int r, const RowIn& in) {
+    // row prefix of one row (cost pairs c0, c1 per lane and sub-pass) into the
+    // row buffer, then CA_x of the lane's output column
+    auto finish_row = [&](int r, const uint32_t (&c0)[NS], const uint32_t (&c1)[NS],
+                          const uint32_t (&p1)[NS], uint32_t am) -> uint32_t {
       const int y = ya + r;
       uint32_t carry = 0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const uint32_t c0 = cost(in.b[s].x, in.o[s].x), c1 = cost(in.b[s].y, in.o[s].y);
-        const uint32_t p1 = wave_scan_incl(c0 + c1) + carry;
-        if (NS > 1) carry = __builtin_amdgcn_readlane(p1, 63);
-        *reinterpret_cast<u32x2*>(&s_row[wave][s * 128 + 2 * lane]) = u32x2{p1 - c1, p1};
+        const uint32_t p = p1[s] + carry;
+        if (NS > 1) carry = __builtin_amdgcn_readlane(p, 63);
+        *reinterpret_cast<u32x2*>(&s_row[wave][s * 128 + 2 * lane]) = u32x2{p - c1[s], p};
         if (DBG && dbg && d == a.dlo && y >= y0 && y < y1) {
           const int xc = x0 - hx + s * 128 + 2 * lane;
-          if (xc >= x0 && xc < x0 + kTX && xc < X) a.dbg_cost[(size_t)y * X + xc] = (uint16_t)c0;
+          if (xc >= x0 && xc < x0 + kTX && xc < X) a.dbg_cost[(size_t)y * X + xc] = (uint16_t)c0[s];
           if (xc + 1 >= x0 && xc + 1 < x0 + kTX && xc + 1 < X)
-            a.dbg_cost[(size_t)y * X + xc + 1] = (uint16_t)c1;
+            a.dbg_cost[(size_t)y * X + xc + 1] = (uint16_t)c1[s];
         }
       }
       WAVE_LDS_ORDER();
-      const int m = in.am & 255u, n = (in.am >> 8) & 255u;
+      const int m = am & 255u, n = (am >> 8) & 255u;
       const uint32_t cax = s_row[wave][lane + hx + n] - s_row[wave][lane + hx - m - 1];
-      if (DBG && dbg && d == a.dlo && x < X && y >= y0 && y < y1) a.dbg_cax[(size_t)y * X + x] = cax;
-      s_plane[(r + 1) * 64 + lane] = cax;
       WAVE_LDS_ORDER();
+      if (DBG && dbg && d == a.dlo && x < X && y >= y0 && y < y1) a.dbg_cax[(size_t)y * X + x] = cax;
+      return cax;
     };
-    RowIn ra_in, rb_in;
-    if (wave < nb) load_row(wave, ra_in);
-    for (int r = wave; r < nb; r += 2 * kWaves) {
-      const bool has_b = r + kWaves < nb;
-      if (has_b) load_row(r + kWaves, rb_in);
-      do_row(r, ra_in);
-      if (has_b) {
-        if (r + 2 * kWaves < nb) load_row(r + 2 * kWaves, ra_in);
-        do_row(r + kWaves, rb_in);
+    uint32_t run = 0;
+    // the partner of row r is r + 1, or r itself (loaded, never stored) at
+    // the end of an odd segment
+    auto partner = [&](int r) { return r + 1 < r1 ? r + 1 : r; };
+    auto process_pair = [&](int r, const RowIn& A, const RowIn& B) {
+      uint32_t ca0[NS], ca1[NS], cb0[NS], cb1[NS], pa[NS], pb[NS];
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        ca0[s] = cost(A.b[s].x, A.o[s].x);
+        ca1[s] = cost(A.b[s].y, A.o[s].y);
+        cb0[s] = cost(B.b[s].x, B.o[s].x);
+        cb1[s] = cost(B.b[s].y, B.o[s].y);
       }
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        pa[s] = wave_scan_incl(ca0[s] + ca1[s]);
+        pb[s] = wave_scan_incl(cb0[s] + cb1[s]);
+      }
+      run += finish_row(r, ca0, ca1, pa, A.am);
+      s_plane[(r + 1) * 64 + lane] = run;
+      if (r + 1 < r1) {
+        run += finish_row(r + 1, cb0, cb1, pb, B.am);
+        s_plane[(r + 2) * 64 + lane] = run;
+      }
+    };
+    RowIn a0, b0, a1, b1;  // two buffer sets, used in turn
+    if (r0 < r1) {
+      load_row(r0, a0);
+      load_row(partner(r0), b0);
     }
+    for (int r = r0; r < r1; r += 4) {
+      if (r + 2 < r1) {
+        load_row(r + 2, a1);
+        load_row(partner(r + 2), b1);
+      }
+      process_pair(r, a0, b0);
+      if (r + 2 >= r1) break;
+      if (r + 4 < r1) {
+        load_row(r + 4, a0);
+        load_row(partner(r + 4), b0);
+      }
+      process_pair(r + 2, a1, b1);
+    }
+    s_seg[wave][c] = run;
     __syncthreads();
-    // ---- column pass: segment sums, segment offsets, prefix in place
-    uint32_t acc = 0;
-#pragma unroll 8
-    for (int r = r0; r < r1; ++r) acc += s_plane[(r + 1) * 64 + c];
-    s_seg[wave][c] = acc;
-    __syncthreads();
+    // ---- column pass: add the sum of the segments above to this segment
     uint32_t off = 0;
 #pragma unroll
     for (int s = 0; s < kWaves; ++s) {
       const uint32_t v = s_seg[s][c];
       off += s < wave ? v : 0u;
     }
+    if (wave > 0) {
 #pragma unroll 8
-    for (int r = r0; r < r1; ++r) {
-      off += s_plane[(r + 1) * 64 + c];
-      s_plane[(r + 1) * 64 + c] = off;
+      for (int r = r0; r < r1; ++r) s_plane[(r + 1) * 64 + c] += off;
     }
     __syncthreads();
     // ---- vertical window and WTA for this wave's output rows

@@ -286,8 +286,10 @@ void launch_match_k(const Plan& pl, const MatchArgs& a, dim3 grid, hipStream_t s
   }
 }
 
-void launch_match(const Plan& pl, const MatchArgs& a, int npair, hipStream_t s) {
-  dim3 grid(pl.nstrips, pl.nbands * a.nchunk, 2 * npair);
+void launch_match(const Plan& pl, MatchArgs a, int npair, hipStream_t s) {
+  a.nstrips = pl.nstrips;
+  a.ngroups = pl.nstrips * pl.nbands * 2 * npair;
+  dim3 grid((unsigned)(((a.ngroups + kXcds - 1) / kXcds) * kXcds * a.nchunk));
   const bool dbg = a.dbg_cost != nullptr;
   switch (pl.ns) {
     case 1: dbg ? launch_match_k<1, true>(pl, a, grid, s) : launch_match_k<1, false>(pl, a, grid, s); break;
@@ -324,7 +326,7 @@ int run(stereo_ctx* c, Plan& pl, const PairPtrs& pp, int npair, bool keep, bool 
                      0, s, pp, pl.W, pl.H, X, Y, pl.half);
   mark(1);
   hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + kFeatRows - 1) / kFeatRows, 2 * npair),
-                     dim3(64, kFeatRows), 0,
+                     dim3(64, 16), 0,
                      s, pl.half, X, Y, pl.p.color_delta, pl.p.arm_x, pl.p.arm_y, pl.XP, pl.pad,
                      pl.XA, pl.pk, pl.arms);
   mark(2);
