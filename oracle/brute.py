@@ -219,3 +219,42 @@ def disparity(left, right, dmax, lambda_ad, lambda_mc, S, delta, ax, ay, T):
     return dict(tables=(tad, tmc), gray_l=gl, half_l=hl, half_r=hr, census_l=cl, census_r=cr,
                 arms_l=al, arms_r=ar, disp_l=dl, disp_r=dr, min_l=ml, min_r=mr, gcp=g,
                 median=md, filled=fl, out=out)
+
+
+# ---------------------------------------------------------------- soft head
+# The differentiable head's forward, pixel by pixel: float half images from
+# explicit 3x3 block lists, the cost from math.exp, the aggregate as a mean
+# over the explicit cross-region cell list, and the soft-argmin with the
+# largest logit subtracted before math.exp.
+
+def soft_half(rgb):
+    """Float half image of float RGB rows (gray weights 77/150/29 over 256)."""
+    H, W = len(rgb), len(rgb[0])
+    g = [[(77.0 * p[0] + 150.0 * p[1] + 29.0 * p[2]) / 256.0 for p in row] for row in rgb]
+    X, Y = (W + 1) // 2, (H + 1) // 2
+    return [[sum(g[clamp(2 * y + j, 0, H - 1)][clamp(2 * x + i, 0, W - 1)]
+                 for j in (-1, 0, 1) for i in (-1, 0, 1)) / 9.0
+             for x in range(X)] for y in range(Y)]
+
+
+def soft_cost(hl, hr, cl, cr, x, y, d, lam_ad, lam_c):
+    if x - d < 0:
+        return 2.0
+    ad = 255.0 * abs(hl[y][x] - hr[y][x - d])
+    h = popcount(cl[y][x] ^ cr[y][x - d])
+    return (1.0 - math.exp(-ad / lam_ad)) + (1.0 - math.exp(-h / lam_c))
+
+
+def soft_d_hat(hl, hr, cl, cr, a, D, lam_ad, lam_c, tau):
+    Y, X = len(hl), len(hl[0])
+    out = [[0.0] * X for _ in range(Y)]
+    for y in range(Y):
+        for x in range(X):
+            cells = cross_region(a, x, y)
+            means = [sum(soft_cost(hl, hr, cl, cr, cx, cy, d, lam_ad, lam_c)
+                         for cx, cy in cells) / len(cells) for d in range(D)]
+            logits = [-v / tau for v in means]
+            top = max(logits)
+            w = [math.exp(z - top) for z in logits]
+            out[y][x] = sum(d * wd for d, wd in enumerate(w)) / sum(w)
+    return out
