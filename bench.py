@@ -44,6 +44,10 @@ def parse():
     ap.add_argument("--latency-frames", type=int, default=100)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000,
+                    help="requests of the served stream (0 skips it)")
+    ap.add_argument("--soft-steps", type=int, default=10,
+                    help="timed steps of the differentiable head (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -107,6 +111,106 @@ def cpu_baseline(pair, seconds):
             "kind": "oracle",
             "sample": f"{frames} full {W}x{H} Dmax={DMAX} frames in {el:.1f} s",
             "mde_per_s": round(W * H * DMAX * fps / 1e6, 2)}
+
+
+def soft_leg(sm, steps):
+    """Differentiable head on 4 x 1436x992, Dmax = 145 (float [0,1] pairs of
+    the same generator, seeds 400-403): pairs per second of the forward alone
+    and of forward + L1 loss + backward to both images and both weights."""
+    import numpy as np
+    import torch
+    from paper_2212_00488_amd.soft import l1_loss, soft_disparity
+    from paper_2212_00488_amd.synth import make_pair
+
+    pairs = [make_pair(W, H, DMAX, segments=40, textureless=0.1, seed=400 + i) for i in range(4)]
+    dev = torch.device("cuda:0")
+    L = torch.from_numpy(np.stack([p.left for p in pairs])).to(dev).float().div_(255.0)
+    R = torch.from_numpy(np.stack([p.right for p in pairs])).to(dev).float().div_(255.0)
+    G = torch.from_numpy(np.stack([p.gt for p in pairs]).astype(np.int16)).to(dev)
+    M = torch.from_numpy(np.stack([p.nonocc for p in pairs]).astype(np.uint8)).to(dev)
+    lam = torch.tensor([10.0, 30.0], device=dev, requires_grad=True)
+    L.requires_grad_(True)
+    R.requires_grad_(True)
+    ctx = sm.Stereo(0)
+    prm = sm.binding.soft_default_params()
+
+    def step():
+        L.grad = R.grad = lam.grad = None
+        d = soft_disparity(ctx, L, R, lam, DMAX, prm)
+        l1_loss(ctx, d, G, M).backward()
+
+    def fwd():
+        with torch.no_grad():
+            soft_disparity(ctx, L, R, lam, DMAX, prm)
+
+    out = {}
+    for name, fn in (("forward", fwd), ("forward_backward", step)):
+        for _ in range(2):
+            fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        for _ in range(steps):
+            fn()
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b) / steps
+        out[name] = {"ms_per_step": round(ms, 4), "pairs_per_s": round(4 * 1000.0 / ms, 2)}
+    ctx.close()
+    return out
+
+
+SERVE_SHAPES = [(640, 480, 64), (1436, 992, 145), (1920, 1080, 256), (2872, 1984, 290)]
+SERVE_RATE = 120.0  # requests per second, Poisson arrivals
+
+
+def serve_leg(n_requests):
+    """Mixed-resolution request stream through the serving runtime: shapes
+    drawn uniformly from SERVE_SHAPES, exponential inter-arrival times at
+    SERVE_RATE (arrival seed 600), 4 slots, admission budget of two of the
+    largest cost volumes.  Inputs come from a pool of two synthetic pairs per
+    shape (seeds 10000 + 10 k + j) in page-locked host memory; each request
+    uploads its pair, runs the resident graph and copies the map back to
+    host memory, all inside the measured latency."""
+    import numpy as np
+    import torch
+    from paper_2212_00488_amd.serve import Server, replay
+    from paper_2212_00488_amd.synth import make_pair
+
+    rng = np.random.default_rng(600)
+    kinds = rng.integers(0, len(SERVE_SHAPES), size=n_requests)
+    which = rng.integers(0, 2, size=n_requests)
+    arrivals = np.cumsum(rng.exponential(1.0 / SERVE_RATE, size=n_requests))
+    pool = {}
+    for k, (w, h, dm) in enumerate(SERVE_SHAPES):
+        for j in range(2):
+            p = make_pair(w, h, dm, segments=40, textureless=0.1, seed=10000 + 10 * k + j)
+            lt = torch.from_numpy(p.left).pin_memory()
+            rt = torch.from_numpy(p.right).pin_memory()
+            pool[(k, j)] = (lt, rt)
+    frames = [(pool[(k, j)][0].numpy(), pool[(k, j)][1].numpy()) for k, j in zip(kinds, which)]
+    dmaxes = [SERVE_SHAPES[k][2] for k in kinds]
+    big = max(((w + 1) // 2) * ((h + 1) // 2) * ((d + 1) // 2) * 4 for w, h, d in SERVE_SHAPES)
+    srv = Server(0, slots=4, mem_budget=2 * big)
+    # warm: one frame of each shape on each slot builds the resident plans and graphs
+    warm = [(pool[(k, 0)][0].numpy(), pool[(k, 0)][1].numpy()) for k in range(4) for _ in range(4)]
+    replay(srv, warm, np.zeros(len(warm)), [SERVE_SHAPES[k][2] for k in range(4) for _ in range(4)])
+    rep, _ = replay(srv, frames, arrivals, dmaxes)
+    srv.close()
+    lat = rep.latency_ms
+    per_shape = {}
+    for k, (w, h, d) in enumerate(SERVE_SHAPES):
+        m = kinds == k
+        per_shape[f"{w}x{h}_d{d}"] = {"n": int(m.sum()),
+                                      "p50_ms": round(float(np.percentile(lat[m], 50)), 3),
+                                      "p99_ms": round(float(np.percentile(lat[m], 99)), 3)}
+    return {"requests": n_requests, "rate_per_s": SERVE_RATE, "slots": 4,
+            "throughput_per_s": round(rep.throughput, 2),
+            "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
+                           "p99": round(float(np.percentile(lat, 99)), 3),
+                           "max": round(float(lat.max()), 3)},
+            "per_shape": per_shape,
+            "host_memory": "page-locked inputs, host output copy included"}
 
 
 def main():
@@ -189,6 +293,18 @@ def main():
                      "avg_launch_ms": round(stage_ms["cost_aggregate_wta"], 5)},
     }
     ctx.close()
+    if args.serve_requests > 0:
+        sv = serve_leg(args.serve_requests)
+        # the served 1436x992 frames (upload and host copy included) against the
+        # plain single-frame device latency of the same shape measured above
+        sv["p99_1436x992_vs_plain"] = round(
+            sv["per_shape"]["1436x992_d145"]["p99_ms"] / res["latency_ms"]["p99"], 3)
+        res["serving"] = sv
+    if args.soft_steps > 0:
+        soft = soft_leg(sm, args.soft_steps)
+        for v in soft.values():
+            v["vs_plain"] = round(v["pairs_per_s"] / fps, 4)
+        res["differentiable"] = {"workload": "4 x 1436x992 float RGB, Dmax=145, tau 0.1", **soft}
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(pair, args.cpu_seconds)
     print(json.dumps(res), flush=True)

@@ -149,6 +149,137 @@ int stereo_get_intermediate(stereo_ctx* ctx, int which, int d, void* dst, size_t
 #define STEREO_NUM_STAGES 6
 int stereo_stage_times(stereo_ctx* ctx, double* ms, int* calls, int reset);
 
+
+/* ------------------------------------------------------------------------
+ * Differentiable soft-argmin head.
+ *
+ * A float version of the left-based path that is smooth in the image
+ * intensities and in the two cost weights, for training them by gradient
+ * descent.  Per pair: gray (77 R + 150 G + 29 B) / 256 and the 3x3 mean at
+ * (2x, 2y) in float (Eq. 2, unrounded); cost (Eq. 3-5 in robust form on the
+ * 0..255 brightness scale)
+ *   C(x,y,d) = (1 - exp(-255 |L(x,y) - R(x-d,y)| / lambda_AD))
+ *            + (1 - exp(-H(x,y,d) / lambda_census)),   C = 2 for x - d < 0,
+ * with H the census Hamming distance; the sum of C over the cross region of
+ * (x,y) (Eq. 7-8) divided by its pixel count |S(x,y)|; and
+ *   d_hat(x,y) = sum_d d p_d,  p = softmax over d in [0, D-1] of -mean / tau.
+ * The census strings and the arms are those of the integer path on the
+ * images quantised to floor(255 v + 1/2) (float32 arithmetic, clamped), and
+ * are not differentiated.  Aggregation sums fixed-point costs (C scaled by
+ * 2^k, rounded; k is the largest that keeps every cross-region sum below
+ * 2^31, k = 18 for the default arms): |error of the mean| <= 2^-(k+1).
+ *
+ * Shared conventions: left/right are device float [n][H][W][3] RGB in [0,1],
+ * contiguous per batch; half-resolution maps are device float [n][Y][X],
+ * X = ceil(W/2), Y = ceil(H/2), D = ceil(Dmax/2); `lambdas` is a device
+ * float[2] {lambda_AD, lambda_census}, both > 0.  Inputs must be finite.
+ * Results are deterministic for fixed inputs.
+ * ---------------------------------------------------------------------- */
+typedef struct stereo_soft_params {
+  uint32_t size;        /* must equal sizeof(stereo_soft_params)                     */
+  float tau;            /* softmax temperature on the mean cost; >= 0.025            */
+  int32_t color_delta;  /* delta of the frozen arms (Sec. III-C), 0..256             */
+  int32_t arm_x;        /* per-side cap of m, n; 0..31                               */
+  int32_t arm_y;        /* per-side cap of M, N; 0..63                               */
+  int32_t slab;         /* disparities recomputed per backward slab; 0 = automatic   */
+} stereo_soft_params;
+
+/* tau = 0.1, delta = 13, arm caps 21 and 31, automatic slab. */
+void stereo_soft_default_params(stereo_soft_params* p);
+
+/* Forward of n pairs (1..64): d_hat [n][Y][X] (half-resolution disparity) and
+ * lse2 [n][Y][X] = log2 of the softmax normaliser in the kernel's scaling,
+ * which stereo_soft_backward needs; both device float, caller-owned. */
+int stereo_soft_forward(stereo_ctx* ctx, const float* left, const float* right, int n, int W,
+                        int H, int Dmax, const float* lambdas, const stereo_soft_params* params,
+                        float* d_hat, float* lse2, hipStream_t stream);
+
+/* Gradient of a scalar loss L given g_dhat = dL/dd_hat [n][Y][X] (device):
+ * writes g_left, g_right (device float [n][H][W][3]) and g_lambdas (device
+ * float[2]: dL/dlambda_AD, dL/dlambda_census), all overwritten, not
+ * accumulated.  d_hat and lse2 are the forward's outputs for the same
+ * inputs.  The adjoint recomputes the aggregate for slabs of disparities
+ * and runs the window sums backward (difference arrays and prefix sums over
+ * the frozen arms); no cost volume is stored.  Scratch grows with the slab:
+ * 2 * n * X * Y * 4 bytes per disparity of a slab. */
+int stereo_soft_backward(stereo_ctx* ctx, const float* left, const float* right, int n, int W,
+                         int H, int Dmax, const float* lambdas, const stereo_soft_params* params,
+                         const float* d_hat, const float* lse2, const float* g_dhat,
+                         float* g_left, float* g_right, float* g_lambdas, hipStream_t stream);
+
+/* L1 training loss of the head: the mean over the batch of, per pair, the
+ * mean of |2 d_hat(x,y) - GT(2x,2y)| over pixels with nonocc(2x,2y) != 0
+ * (0 for a pair without such pixels).  gt: device int16 [n][H][W]
+ * full-resolution disparity; nonocc: device uint8 [n][H][W].  loss: device
+ * float[1]. */
+int stereo_soft_l1_loss(stereo_ctx* ctx, const float* d_hat, const int16_t* gt,
+                        const uint8_t* nonocc, int n, int W, int H, float* loss,
+                        hipStream_t stream);
+
+/* Its gradient: g_dhat [n][Y][X] = gscale * dL/dd_hat, sign(0) taken as 0;
+ * gscale is a device float[1] (the upstream gradient) or NULL for 1. */
+int stereo_soft_l1_grad(stereo_ctx* ctx, const float* d_hat, const int16_t* gt,
+                        const uint8_t* nonocc, int n, int W, int H, const float* gscale,
+                        float* g_dhat, hipStream_t stream);
+
+
+/* ------------------------------------------------------------------------
+ * Serving runtime.
+ *
+ * A persistent worker thread serves frames of mixed shapes as they arrive
+ * (the real-time use of the method, Sec. I and Sec. V).  It keeps, per shape
+ * and per slot, device buffers, a plan and a HIP graph of the whole path
+ * resident; it admits frames in submission order whenever a slot (a stream
+ * of its own) is free and the frames in flight, counted by their
+ * cost-volume size X*Y*D*4 bytes, stay within mem_budget (a frame alone in
+ * flight is always admitted).  Frames in different slots overlap on the
+ * device and never share scratch, so each result is bit-identical to
+ * stereo_disparity's for the same frame.  Times are host steady-clock
+ * milliseconds since the server was created.
+ * ---------------------------------------------------------------------- */
+typedef struct stereo_server stereo_server; /* opaque */
+
+typedef struct stereo_server_config {
+  uint32_t size;       /* must equal sizeof(stereo_server_config)               */
+  int32_t device;      /* HIP device                                            */
+  int32_t slots;       /* frames in flight at most, 1..16, one stream each      */
+  uint64_t mem_budget; /* admission budget in bytes of X*Y*D*4; 0 = none        */
+  stereo_params params;/* method parameters for every frame (flags ignored)     */
+} stereo_server_config;
+
+typedef struct stereo_server_result {
+  uint64_t tag;        /* the submit call's tag                                 */
+  int32_t status;      /* 0 or a STEREO_E* code (the frame was not computed)    */
+  int32_t slot;        /* slot that served it (-1 on error)                      */
+  double t_submit_ms;  /* stereo_server_submit called                           */
+  double t_admit_ms;   /* work enqueued on the slot's stream                    */
+  double t_done_ms;    /* output copied to the caller's buffer                  */
+} stereo_server_result;
+
+/* 4 slots, no budget, the paper's parameters. */
+void stereo_server_default_config(stereo_server_config* cfg);
+
+int stereo_server_create(stereo_server** out, const stereo_server_config* cfg);
+
+/* Queues one frame.  left, right: HOST uint8 [H][W][3] (page-locked memory
+ * makes the upload asynchronous); out: HOST int16 [H][W].  All three must
+ * stay valid until the frame's result has been returned by
+ * stereo_server_poll.  Returns STEREO_EINVAL for bad arguments or after
+ * destroy began. */
+int stereo_server_submit(stereo_server* srv, const uint8_t* left, const uint8_t* right, int W,
+                         int H, int Dmax, int16_t* out, uint64_t tag);
+
+/* Moves up to max finished results into res, waiting up to timeout_ms for
+ * the first one; returns how many (0 if none finished in time). */
+int stereo_server_poll(stereo_server* srv, stereo_server_result* res, int max, int timeout_ms);
+
+/* Text of the last error the worker met ("" if none). */
+const char* stereo_server_last_error(stereo_server* srv);
+
+/* Serves every queued frame, then frees everything.  NULL is a no-op.
+ * Results not yet polled are dropped. */
+void stereo_server_destroy(stereo_server* srv);
+
 #ifdef __cplusplus
 }
 #endif

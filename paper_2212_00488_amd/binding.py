@@ -44,6 +44,24 @@ class Params(ctypes.Structure):
                 ("flags", ctypes.c_uint32)]
 
 
+class SoftParams(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("tau", ctypes.c_float),
+                ("color_delta", ctypes.c_int32), ("arm_x", ctypes.c_int32),
+                ("arm_y", ctypes.c_int32), ("slab", ctypes.c_int32)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("size", ctypes.c_uint32), ("device", ctypes.c_int32),
+                ("slots", ctypes.c_int32), ("mem_budget", ctypes.c_uint64),
+                ("params", Params)]
+
+
+class ServerResult(ctypes.Structure):
+    _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("slot", ctypes.c_int32),
+                ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
+                ("t_done_ms", ctypes.c_double)]
+
+
 class StereoError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__(f"stereo error {code}: {msg}")
@@ -79,6 +97,29 @@ def lib():
         L.stereo_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int), I]
         L.stereo_stage_times.restype = I
+        SP = ctypes.POINTER(SoftParams)
+        L.stereo_soft_default_params.argtypes = [SP]
+        L.stereo_soft_default_params.restype = None
+        L.stereo_soft_forward.argtypes = [P, P, P, I, I, I, I, P, SP, P, P, P]
+        L.stereo_soft_forward.restype = I
+        L.stereo_soft_backward.argtypes = [P, P, P, I, I, I, I, P, SP, P, P, P, P, P, P, P]
+        L.stereo_soft_backward.restype = I
+        L.stereo_soft_l1_loss.argtypes = [P, P, P, P, I, I, I, P, P]
+        L.stereo_soft_l1_loss.restype = I
+        L.stereo_soft_l1_grad.argtypes = [P, P, P, P, I, I, I, P, P, P]
+        L.stereo_soft_l1_grad.restype = I
+        L.stereo_server_default_config.argtypes = [ctypes.POINTER(ServerConfig)]
+        L.stereo_server_default_config.restype = None
+        L.stereo_server_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(ServerConfig)]
+        L.stereo_server_create.restype = I
+        L.stereo_server_submit.argtypes = [P, P, P, I, I, I, P, ctypes.c_uint64]
+        L.stereo_server_submit.restype = I
+        L.stereo_server_poll.argtypes = [P, ctypes.POINTER(ServerResult), I, I]
+        L.stereo_server_poll.restype = I
+        L.stereo_server_last_error.argtypes = [P]
+        L.stereo_server_last_error.restype = ctypes.c_char_p
+        L.stereo_server_destroy.argtypes = [P]
+        L.stereo_server_destroy.restype = None
         _lib = L
     return _lib
 
@@ -91,11 +132,29 @@ def default_params(**overrides) -> Params:
     return p
 
 
+def soft_default_params(**overrides) -> SoftParams:
+    p = SoftParams()
+    lib().stereo_soft_default_params(ctypes.byref(p))
+    for k, v in overrides.items():
+        setattr(p, k, v)
+    return p
+
+
 def _stream_handle(stream):
     import torch
     if stream is None:
         stream = torch.cuda.current_stream()
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_dev(t, name, dtype, shape=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise TypeError(f"{name} must be a contiguous {dtype} tensor")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} has shape {tuple(t.shape)}, expected {tuple(shape)}")
 
 
 def _check_image(t, name):
@@ -197,3 +256,74 @@ class Stereo:
                                            _stream_handle(stream))
         self._raise(rc)
         return buf
+
+    # ------------------------------------------------------ soft-argmin head
+    def soft_forward(self, left, right, lambdas, dmax: int, params: SoftParams | None = None,
+                     stream=None):
+        """(d_hat, lse2), float [n][Y][X] each, of float [n][H][W][3] pairs."""
+        import torch
+        n, H, W, _ = left.shape
+        _check_dev(left, "left", torch.float32, (n, H, W, 3))
+        _check_dev(right, "right", torch.float32, (n, H, W, 3))
+        _check_dev(lambdas, "lambdas", torch.float32, (2,))
+        X, Y = (W + 1) // 2, (H + 1) // 2
+        d_hat = torch.empty((n, Y, X), dtype=torch.float32, device=left.device)
+        lse2 = torch.empty_like(d_hat)
+        rc = lib().stereo_soft_forward(self._h, left.data_ptr(), right.data_ptr(), n, W, H,
+                                       int(dmax), lambdas.data_ptr(),
+                                       ctypes.byref(params) if params is not None else None,
+                                       d_hat.data_ptr(), lse2.data_ptr(), _stream_handle(stream))
+        self._raise(rc)
+        return d_hat, lse2
+
+    def soft_backward(self, left, right, lambdas, dmax: int, d_hat, lse2, g_dhat,
+                      params: SoftParams | None = None, stream=None):
+        """(g_left, g_right, g_lambdas) of the head given dL/dd_hat."""
+        import torch
+        n, H, W, _ = left.shape
+        _check_dev(left, "left", torch.float32, (n, H, W, 3))
+        _check_dev(right, "right", torch.float32, (n, H, W, 3))
+        _check_dev(lambdas, "lambdas", torch.float32, (2,))
+        for t, nm in ((d_hat, "d_hat"), (lse2, "lse2"), (g_dhat, "g_dhat")):
+            _check_dev(t, nm, torch.float32, (n, (H + 1) // 2, (W + 1) // 2))
+        g_left = torch.empty_like(left)
+        g_right = torch.empty_like(right)
+        g_lam = torch.empty(2, dtype=torch.float32, device=left.device)
+        rc = lib().stereo_soft_backward(
+            self._h, left.data_ptr(), right.data_ptr(), n, W, H, int(dmax), lambdas.data_ptr(),
+            ctypes.byref(params) if params is not None else None, d_hat.data_ptr(),
+            lse2.data_ptr(), g_dhat.data_ptr(), g_left.data_ptr(), g_right.data_ptr(),
+            g_lam.data_ptr(), _stream_handle(stream))
+        self._raise(rc)
+        return g_left, g_right, g_lam
+
+    def l1_loss(self, d_hat, gt, nonocc, stream=None):
+        """Device float[1] loss of the head (gt int16, nonocc uint8, [n][H][W])."""
+        import torch
+        n, H, W = gt.shape
+        _check_dev(d_hat, "d_hat", torch.float32, (n, (H + 1) // 2, (W + 1) // 2))
+        _check_dev(gt, "gt", torch.int16)
+        _check_dev(nonocc, "nonocc", torch.uint8, (n, H, W))
+        loss = torch.empty(1, dtype=torch.float32, device=d_hat.device)
+        rc = lib().stereo_soft_l1_loss(self._h, d_hat.data_ptr(), gt.data_ptr(),
+                                       nonocc.data_ptr(), n, W, H, loss.data_ptr(),
+                                       _stream_handle(stream))
+        self._raise(rc)
+        return loss
+
+    def l1_grad(self, d_hat, gt, nonocc, gscale=None, stream=None):
+        """dL/dd_hat of l1_loss, times the device scalar gscale (None = 1)."""
+        import torch
+        n, H, W = gt.shape
+        _check_dev(d_hat, "d_hat", torch.float32, (n, (H + 1) // 2, (W + 1) // 2))
+        _check_dev(gt, "gt", torch.int16)
+        _check_dev(nonocc, "nonocc", torch.uint8, (n, H, W))
+        if gscale is not None:
+            _check_dev(gscale, "gscale", torch.float32)
+        g = torch.empty_like(d_hat)
+        rc = lib().stereo_soft_l1_grad(self._h, d_hat.data_ptr(), gt.data_ptr(),
+                                       nonocc.data_ptr(), n, W, H,
+                                       gscale.data_ptr() if gscale is not None else None,
+                                       g.data_ptr(), _stream_handle(stream))
+        self._raise(rc)
+        return g

@@ -8,13 +8,15 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libstereo_mi355x.so")
-SOURCES = [os.path.join(PKG, "csrc", "stereo.hip")]
-HEADERS = [os.path.join(PKG, "csrc", "kernels.hip.h"), os.path.join(ROOT, "include", "stereo.h")]
+SOURCES = [os.path.join(PKG, "csrc", n) for n in ("stereo.hip", "soft.hip", "server.hip")]
+HEADERS = [os.path.join(PKG, "csrc", n) for n in ("kernels.hip.h", "soft.hip.h", "context.h", "common.h",
+                                                 "pipeline.h")] + [
+    os.path.join(ROOT, "include", "stereo.h")]
 
 
 def hipcc_command(out: str = LIB) -> list[str]:
     return ["hipcc", "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-            "-Wall", "-I" + os.path.join(ROOT, "include"),
+            "-Wall", "-Wno-unused-function", "-I" + os.path.join(ROOT, "include"),
             # packed fp32 instructions stay off in all device code
             "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
             *SOURCES, "-o", out]

@@ -12,9 +12,13 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-namespace stereo_dev {
+#include "common.h"
 
-constexpr int kMaxPairs = 8;      // pairs per launch (batched entry point)
+namespace stereo_dev {
+// Internal linkage: each source of the library that launches a kernel
+// carries its own copy (no relocatable device code).
+namespace {
+
 constexpr int kTX = 64;           // k_match strip width = one wave
 constexpr int kWaves = 16;        // k_match workgroup = 16 waves
 constexpr int kThreads = kWaves * 64;
@@ -22,11 +26,6 @@ constexpr int kKMax = 34;         // most output rows per k_match thread (band <
 constexpr int kLdsBytes = 163840; // LDS per workgroup on gfx950
 constexpr int kXcds = 8;          // accelerator complex dies, each with its own L2
 
-struct PairPtrs {
-  const uint8_t* left[kMaxPairs];
-  const uint8_t* right[kMaxPairs];
-  int16_t* out[kMaxPairs];
-};
 
 __device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
 __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
@@ -641,4 +640,5 @@ __global__ void __launch_bounds__(256) k_upscale(PairPtrs pp, const int16_t* __r
   }
 }
 
+}  // namespace
 }  // namespace stereo_dev

@@ -1,0 +1,370 @@
+// Serving runtime of the integer path: a persistent worker thread takes
+// stereo frames of mixed shapes as they are submitted, keeps per-(shape,
+// slot) device buffers, plans and captured HIP graphs resident, admits
+// frames in arrival order while a slot (a stream of its own) is free and the
+// cost-volume budget of the frames in flight allows, and returns each result
+// with its submit / admit / done times.  Frames in different slots overlap
+// on the device; no two in-flight frames share scratch.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <tuple>
+#include <vector>
+
+#include "context.h"
+#include "pipeline.h"
+#include "stereo.h"
+
+using namespace stereo_host;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Request {
+  const uint8_t* left;
+  const uint8_t* right;
+  int16_t* out;
+  int W, H, Dmax;
+  uint64_t tag;
+  size_t volume;  // X * Y * D * 4 bytes: the admission measure
+  Clock::time_point t_submit, t_admit;
+};
+
+// Resident state of one shape on one slot: device inputs and output, pinned
+// staging of the output, the plan and the captured graph of the path.
+struct Exec {
+  uint8_t* d_left = nullptr;
+  uint8_t* d_right = nullptr;
+  int16_t* d_out = nullptr;
+  int16_t* h_out = nullptr;  // pinned
+  Plan* plan = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+struct Slot {
+  hipStream_t stream = nullptr;
+  hipEvent_t done = nullptr;
+  bool busy = false;
+  Request req{};
+  Exec* ex = nullptr;
+  std::map<std::tuple<int, int, int>, Exec*> execs;
+};
+
+}  // namespace
+
+struct stereo_server {
+  stereo_server_config cfg{};
+  stereo_params params{};
+  stereo_ctx* ctx = nullptr;
+  std::vector<Slot> slots;
+  Clock::time_point t0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<Request> incoming;          // guarded by mu
+  std::deque<stereo_server_result> done; // guarded by mu
+  std::deque<Request> pending;           // worker only
+  size_t inflight = 0;                   // worker only
+  bool stop = false;                     // guarded by mu
+  std::string err;                       // guarded by mu (errors of the worker)
+  std::thread worker;
+};
+
+namespace {
+
+double ms_since(const stereo_server* s, Clock::time_point t) {
+  return std::chrono::duration<double, std::milli>(t - s->t0).count();
+}
+
+void free_exec(Exec* e) {
+  if (!e) return;
+  if (e->exec) (void)hipGraphExecDestroy(e->exec);
+  if (e->graph) (void)hipGraphDestroy(e->graph);
+  if (e->d_left) (void)hipFree(e->d_left);
+  if (e->d_right) (void)hipFree(e->d_right);
+  if (e->d_out) (void)hipFree(e->d_out);
+  if (e->h_out) (void)hipHostFree(e->h_out);
+  delete e;
+}
+
+// Builds the resident state of (W, H, Dmax) on slot i: buffers, the slot's
+// plan and a graph captured from the path's launch sequence on its stream.
+int make_exec(stereo_server* s, int i, int W, int H, int Dmax, Exec** out) {
+  Slot& sl = s->slots[i];
+  stereo_ctx* c = s->ctx;
+  Exec* e = new Exec();
+  const size_t img = (size_t)W * H * 3, omap = (size_t)W * H * 2;
+  hipError_t he = hipMalloc(&e->d_left, img);
+  if (he == hipSuccess) he = hipMalloc(&e->d_right, img);
+  if (he == hipSuccess) he = hipMalloc(&e->d_out, omap);
+  if (he == hipSuccess) he = hipHostMalloc(reinterpret_cast<void**>(&e->h_out), omap, hipHostMallocDefault);
+  if (he != hipSuccess) {
+    (void)hipGetLastError();
+    free_exec(e);
+    return fail(c, STEREO_ENOMEM, "server buffers for %dx%d: %s", W, H, hipGetErrorString(he));
+  }
+  int rc = get_plan(c, W, H, Dmax, s->params, 1, &sl, &e->plan);
+  if (rc) {
+    free_exec(e);
+    return rc;
+  }
+  stereo_dev::PairPtrs pp{};
+  pp.left[0] = e->d_left;
+  pp.right[0] = e->d_right;
+  pp.out[0] = e->d_out;
+  he = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
+  if (he == hipSuccess) {
+    rc = run(c, *e->plan, pp, 1, false, false, sl.stream);
+    hipError_t ee = hipStreamEndCapture(sl.stream, &e->graph);
+    if (!rc && ee != hipSuccess) rc = fail(c, STEREO_EHIP, "capture: %s", hipGetErrorString(ee));
+  } else {
+    rc = fail(c, STEREO_EHIP, "hipStreamBeginCapture: %s", hipGetErrorString(he));
+  }
+  if (!rc) {
+    he = hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0);
+    if (he != hipSuccess) rc = fail(c, STEREO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(he));
+  }
+  if (rc) {
+    (void)hipGetLastError();
+    free_exec(e);
+    return rc;
+  }
+  *out = e;
+  return 0;
+}
+
+void post(stereo_server* s, const Request& r, int status, int slot, Clock::time_point t_done) {
+  stereo_server_result res{};
+  res.tag = r.tag;
+  res.status = status;
+  res.slot = slot;
+  res.t_submit_ms = ms_since(s, r.t_submit);
+  res.t_admit_ms = status ? res.t_submit_ms : ms_since(s, r.t_admit);
+  res.t_done_ms = ms_since(s, t_done);
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->done.push_back(res);
+  }
+  s->cv_done.notify_all();
+}
+
+// Starts request r on free slot i; returns 0 or an error code (the request
+// is then answered with that status).
+int start(stereo_server* s, int i, Request& r) {
+  Slot& sl = s->slots[i];
+  auto key = std::make_tuple(r.W, r.H, r.Dmax);
+  auto it = sl.execs.find(key);
+  Exec* e = nullptr;
+  if (it == sl.execs.end()) {
+    int rc = make_exec(s, i, r.W, r.H, r.Dmax, &e);
+    if (rc) return rc;
+    sl.execs[key] = e;
+  } else {
+    e = it->second;
+  }
+  const size_t img = (size_t)r.W * r.H * 3, omap = (size_t)r.W * r.H * 2;
+  hipError_t he = hipMemcpyAsync(e->d_left, r.left, img, hipMemcpyHostToDevice, sl.stream);
+  if (he == hipSuccess) he = hipMemcpyAsync(e->d_right, r.right, img, hipMemcpyHostToDevice, sl.stream);
+  if (he == hipSuccess) he = hipGraphLaunch(e->exec, sl.stream);
+  if (he == hipSuccess) he = hipMemcpyAsync(e->h_out, e->d_out, omap, hipMemcpyDeviceToHost, sl.stream);
+  if (he == hipSuccess) he = hipEventRecord(sl.done, sl.stream);
+  if (he != hipSuccess) return fail(s->ctx, STEREO_EHIP, "enqueue: %s", hipGetErrorString(he));
+  r.t_admit = Clock::now();
+  sl.busy = true;
+  sl.req = r;
+  sl.ex = e;
+  return 0;
+}
+
+void worker_main(stereo_server* s) {
+  (void)hipSetDevice(s->cfg.device);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> g(s->mu);
+      bool any_busy = false;
+      for (const Slot& sl : s->slots) any_busy |= sl.busy;
+      if (s->incoming.empty() && s->pending.empty() && !any_busy) {
+        if (s->stop) return;
+        s->cv_work.wait(g, [&] { return s->stop || !s->incoming.empty(); });
+        if (s->stop && s->incoming.empty()) return;
+      }
+      while (!s->incoming.empty()) {
+        s->pending.push_back(s->incoming.front());
+        s->incoming.pop_front();
+      }
+    }
+    bool progressed = false;
+    // completions
+    for (int i = 0; i < (int)s->slots.size(); ++i) {
+      Slot& sl = s->slots[i];
+      if (!sl.busy) continue;
+      hipError_t q = hipEventQuery(sl.done);
+      if (q == hipErrorNotReady) continue;
+      int status = 0;
+      if (q != hipSuccess) {
+        status = STEREO_EHIP;
+        std::lock_guard<std::mutex> g(s->mu);
+        s->err = hipGetErrorString(q);
+      } else {
+        std::memcpy(sl.req.out, sl.ex->h_out, (size_t)sl.req.W * sl.req.H * 2);
+      }
+      sl.busy = false;
+      s->inflight -= sl.req.volume;
+      post(s, sl.req, status, i, Clock::now());
+      progressed = true;
+    }
+    // admission in arrival order: a free slot and room in the budget (a
+    // frame alone in flight is always admitted)
+    while (!s->pending.empty()) {
+      Request& r = s->pending.front();
+      int free_slot = -1;
+      for (int i = 0; i < (int)s->slots.size() && free_slot < 0; ++i)
+        if (!s->slots[i].busy) free_slot = i;
+      if (free_slot < 0) break;
+      if (s->cfg.mem_budget && s->inflight > 0 && s->inflight + r.volume > s->cfg.mem_budget) break;
+      int rc = start(s, free_slot, r);
+      if (rc) {
+        {
+          std::lock_guard<std::mutex> g(s->mu);
+          s->err = s->ctx->err;
+        }
+        post(s, r, rc, -1, Clock::now());
+      } else {
+        s->inflight += r.volume;
+      }
+      s->pending.pop_front();
+      progressed = true;
+    }
+    if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void stereo_server_default_config(stereo_server_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->size = sizeof(stereo_server_config);
+  cfg->device = 0;
+  cfg->slots = 4;
+  cfg->mem_budget = 0;
+  stereo_default_params(&cfg->params);
+}
+
+int stereo_server_create(stereo_server** out, const stereo_server_config* cfg) {
+  if (!out || !cfg) return STEREO_EINVAL;
+  *out = nullptr;
+  if (cfg->size != sizeof(stereo_server_config) || cfg->slots < 1 || cfg->slots > 16)
+    return STEREO_EINVAL;
+  stereo_ctx* c = nullptr;
+  int rc = stereo_create(&c, cfg->device, 0);
+  if (rc) return rc;
+  stereo_params p;
+  rc = common_checks(c, 2, 2, 1, &cfg->params, &p);
+  if (rc) {
+    stereo_destroy(c);
+    return rc;
+  }
+  stereo_server* s = new stereo_server();
+  s->cfg = *cfg;
+  s->params = p;
+  s->params.flags = 0;
+  s->ctx = c;
+  s->slots.resize(cfg->slots);
+  for (Slot& sl : s->slots) {
+    // default-priority streams and events without timing
+    if (hipStreamCreateWithFlags(&sl.stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sl.done, hipEventDisableTiming) != hipSuccess) {
+      (void)hipGetLastError();
+      for (Slot& q : s->slots) {
+        if (q.stream) (void)hipStreamDestroy(q.stream);
+        if (q.done) (void)hipEventDestroy(q.done);
+      }
+      stereo_destroy(c);
+      delete s;
+      return STEREO_EHIP;
+    }
+  }
+  s->t0 = Clock::now();
+  s->worker = std::thread(worker_main, s);
+  *out = s;
+  return 0;
+}
+
+int stereo_server_submit(stereo_server* s, const uint8_t* left, const uint8_t* right, int W, int H,
+                         int Dmax, int16_t* out, uint64_t tag) {
+  if (!s) return STEREO_EINVAL;
+  if (!left || !right || !out) return STEREO_EINVAL;
+  if (W < 2 || H < 2 || W > STEREO_MAX_SIDE || H > STEREO_MAX_SIDE || Dmax < 1 || Dmax > W ||
+      Dmax > STEREO_MAX_DMAX)
+    return STEREO_EINVAL;
+  Request r{};
+  r.left = left;
+  r.right = right;
+  r.out = out;
+  r.W = W;
+  r.H = H;
+  r.Dmax = Dmax;
+  r.tag = tag;
+  r.volume = (size_t)((W + 1) / 2) * ((H + 1) / 2) * ((Dmax + 1) / 2) * 4;
+  r.t_submit = Clock::now();
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->stop) return STEREO_EINVAL;
+    s->incoming.push_back(r);
+  }
+  s->cv_work.notify_one();
+  return 0;
+}
+
+int stereo_server_poll(stereo_server* s, stereo_server_result* res, int max, int timeout_ms) {
+  if (!s || !res || max < 1) return STEREO_EINVAL;
+  std::unique_lock<std::mutex> g(s->mu);
+  if (s->done.empty() && timeout_ms > 0)
+    s->cv_done.wait_for(g, std::chrono::milliseconds(timeout_ms), [&] { return !s->done.empty(); });
+  int n = 0;
+  while (n < max && !s->done.empty()) {
+    res[n++] = s->done.front();
+    s->done.pop_front();
+  }
+  return n;
+}
+
+const char* stereo_server_last_error(stereo_server* s) {
+  if (!s) return "null server";
+  std::lock_guard<std::mutex> g(s->mu);
+  thread_local std::string copy;
+  copy = s->err;
+  return copy.c_str();
+}
+
+void stereo_server_destroy(stereo_server* s) {
+  if (!s) return;
+  {
+    std::lock_guard<std::mutex> g(s->mu);
+    s->stop = true;
+  }
+  s->cv_work.notify_all();
+  if (s->worker.joinable()) s->worker.join();
+  (void)hipSetDevice(s->cfg.device);
+  for (Slot& sl : s->slots) {
+    if (sl.stream) (void)hipStreamSynchronize(sl.stream);
+    for (auto& kv : sl.execs) free_exec(kv.second);
+    if (sl.stream) (void)hipStreamDestroy(sl.stream);
+    if (sl.done) (void)hipEventDestroy(sl.done);
+  }
+  stereo_destroy(s->ctx);
+  delete s;
+}
+
+}  // extern "C"

@@ -1,0 +1,657 @@
+// Device kernels of the differentiable soft-argmin head (gfx950, wave64).
+//
+// The head keeps the cost and the cross-based aggregation of the paper
+// (Eq. 3-5, 7-8) in floating point so that the disparity is a smooth
+// function of the images and of the two cost weights; the census strings
+// and the cross arms (Sec. III-B, III-C) are the integer path's, taken of the
+// quantised images and frozen.
+//
+//   forward   k_soft_prep   RGB float -> float half image, and the uint8 half
+//                           image of the quantised RGB (for k_feat)
+//             k_feat        census and arms (shared with the integer path)
+//             k_soft_pack   float half image + census -> padded pixel planes
+//             k_soft_size   1 / |S(x,y)|, the cross-region pixel count
+//             k_soft_agg    cost C = (1 - e^{-255|dI|/lambda_AD}) +
+//                           (1 - e^{-H/lambda_census}), CA over the cross
+//                           region, and the softmax sums over a d-chunk
+//             k_soft_merge  d_hat = sum d e_d / sum e_d, log2 sum e_d
+//   backward  k_soft_bprep  per-pixel constants of dL/dCA
+//             k_soft_agg    (GCA mode) recomputes CA for a slab of d and
+//                           writes dL/dCA planes
+//             k_soft_tr     transposed window sums (difference arrays +
+//                           prefix sums) back to dL/dC, then dC/d(dI),
+//                           dC/d(lambda) per pixel
+//             k_soft_gimg   dL/d(half image) of both images over the slab
+//             k_soft_gfull  transposed downscale and gray: dL/d(RGB)
+//             k_soft_lam    fixed-order sum of the lambda partials
+//   loss      k_l1_*        mean |2 d_hat - GT(2x,2y)| over non-occluded
+//                           pixels, per pair, averaged over the batch
+//
+// Aggregation runs on costs in fixed point (C * 2^k rounded, k chosen per
+// plan so that every cross-region sum stays below 2^31): the row and column
+// prefix sums then wrap modulo 2^32 and every window difference is the exact
+// sum of the rounded costs, whatever the prefix magnitude.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.hip.h"
+
+namespace stereo_dev {
+// Internal linkage: each source of the library that launches a kernel
+// carries its own copy (no relocatable device code).
+namespace {
+
+constexpr int kSoftBR = 32;  // output rows per k_soft_tr workgroup
+
+__device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+
+// ----------------------------------------------------------- k_soft_prep
+// One thread per half-res pixel of one image (img = 2 pair + {0 left, 1 right}).
+// Float path: gray = (77 R + 150 G + 29 B) / 256, half = mean of the 3x3 block
+// at (2x, 2y), borders clamped.  Integer path: each channel quantised to
+// floor(255 v + 1/2) in float32 (product and sum rounded separately), clamped
+// to 0..255, then the integer gray and (sum + 4) / 9 as in k_prep.
+// grid: (ceil(X/64), ceil(Y/4), 2n), block (64, 4).
+__global__ void __launch_bounds__(256) k_soft_prep(const float* __restrict__ left,
+                                                   const float* __restrict__ right, int W, int H,
+                                                   int X, int Y, float* __restrict__ half_f,
+                                                   uint8_t* __restrict__ half_u8) {
+  const int x = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
+  const int img = blockIdx.z;
+  if (x >= X || y >= Y) return;
+  const float* rgb = ((img & 1) ? right : left) + (size_t)(img >> 1) * H * W * 3;
+  float sf = 0.f;
+  int si = 0;
+#pragma unroll
+  for (int j = -1; j <= 1; ++j) {
+    const float* row = rgb + (size_t)clampi(2 * y + j, 0, H - 1) * W * 3;
+#pragma unroll
+    for (int i = -1; i <= 1; ++i) {
+      const float* p = row + (size_t)clampi(2 * x + i, 0, W - 1) * 3;
+      const float r = p[0], g = p[1], b = p[2];
+      sf += (77.f * r + 150.f * g + 29.f * b) * (1.f / 256.f);
+      int q[3];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float t = floorf(__fadd_rn(__fmul_rn(255.f, p[c]), 0.5f));
+        q[c] = (int)fminf(fmaxf(t, 0.f), 255.f);
+      }
+      si += (77 * q[0] + 150 * q[1] + 29 * q[2] + 128) >> 8;
+    }
+  }
+  const size_t o = (size_t)img * X * Y + (size_t)y * X + x;
+  half_f[o] = sf * (1.f / 9.f);
+  half_u8[o] = (uint8_t)((si + 4) / 9);
+}
+
+// ----------------------------------------------------------- k_soft_pack
+// Padded pixel planes of the soft kernels: {float half value bits, census}
+// at column pads + x of row y; the padding columns are zero (set once).
+// grid: (ceil(X/256), Y, 2n), block 256.
+__global__ void __launch_bounds__(256) k_soft_pack(const float* __restrict__ half_f,
+                                                   const uint32_t* __restrict__ pk, int X, int Y,
+                                                   int XS, int pads, uint2* __restrict__ sp) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, img = blockIdx.z;
+  if (x >= X) return;
+  const size_t i = ((size_t)img * Y + y) * X + x;  // pk of the soft plan is unpadded
+  sp[((size_t)img * Y + y) * XS + pads + x] =
+      make_uint2(__float_as_uint(half_f[i]), (pk[i] >> 16) & 63u);
+}
+
+// ----------------------------------------------------------- k_soft_size
+// 1 / |S(x,y)| for the left image of each pair: |S| = sum over s in
+// [-M, N] of (m + n + 1) at (x, y + s) (Eq. 7-8 applied to a unit cost).
+// grid: (ceil(X/256), Y, n), block 256.
+__global__ void __launch_bounds__(256) k_soft_size(const uint32_t* __restrict__ arms, int X,
+                                                   int Y, int XA, float* __restrict__ inv_size) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, pair = blockIdx.z;
+  if (x >= X) return;
+  const uint32_t* a = arms + (size_t)(2 * pair) * Y * XA;
+  const uint32_t c = a[(size_t)y * XA + x];
+  const int M = (c >> 16) & 255, N = c >> 24;
+  int s = 0;
+  for (int r = y - M; r <= y + N; ++r) {
+    const uint32_t v = a[(size_t)r * XA + x];
+    s += (int)(v & 255u) + (int)((v >> 8) & 255u) + 1;
+  }
+  inv_size[(size_t)pair * X * Y + (size_t)y * X + x] = 1.f / (float)s;
+}
+
+// ------------------------------------------------------------ k_soft_agg
+struct SoftArgs {
+  const uint2* sp;          // [2n][Y][XS] padded pixel planes
+  const uint32_t* arms;     // [2n][Y][XA]
+  const float* lam;         // device [2]: lambda_AD, lambda_census
+  const float* inv_size;    // [n][Y][X]                    (forward)
+  float2* part;             // [n][nchunk][Y][X] {sum e, sum d e}  (forward)
+  const float4* pc;         // [n][Y][X] {w, log2 sum e, d_hat, A}  (GCA)
+  float* gca;               // [nds][n][Y][X] dL/dCA           (GCA)
+  int X, Y, XS, pads, XA, arm_x, arm_y;
+  int nbands, nchunk, dlo, dhi, nstrips, ngroups, npair;
+  float fx;                 // fixed-point scale 2^k of the costs
+  float zc;                 // 2^-k log2(e) / tau: CA_int * inv_size * zc = mean / tau in log2 units
+  uint32_t sp_bytes, arms_bytes;
+};
+
+// Inclusive prefix sum of a float over the 64 lanes of a wave (the DPP
+// steps of wave_scan_incl, in float).
+template <int CTRL, int RMASK>
+__device__ __forceinline__ float dpp_add_f(float v) {
+  return v + __int_as_float(
+                 __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, RMASK, 0xf, false));
+}
+__device__ __forceinline__ float wave_scan_incl_f(float v) {
+  v = dpp_add_f<0x111, 0xf>(v);
+  v = dpp_add_f<0x112, 0xf>(v);
+  v = dpp_add_f<0x114, 0xf>(v);
+  v = dpp_add_f<0x118, 0xf>(v);
+  v = dpp_add_f<0x142, 0xa>(v);
+  v = dpp_add_f<0x143, 0xc>(v);
+  return v;
+}
+
+// One workgroup = one 64-column strip x one band of rows x one pair x one
+// chunk of disparities; 16 waves, the layout of k_match (row pass with a DPP
+// wave scan, running column sums into the LDS plane, segment offsets, window
+// differences).  The cost of a column c at disparity d:
+//   c - d >= 0: C = (2 - exp(-255 |L(c) - R(c-d)| / lambda_AD)) - exp(-H / lambda_census)
+//   c - d <  0: C = 2
+// taken to fixed point.  Output rows of a thread: o0 + wave + 16 k, k < KMAX.
+//   GCA = false: e = 2^{-CA mean / tau (log2 units)}, sums of e and d e per
+//                output pixel over the chunk -> part;
+//   GCA = true : dL/dCA(x,y,d) = A p_d (d - d_hat), p_d = 2^{-z_d - log2 sum e}
+//                -> gca plane of d (slot d - dlo).
+// grid: ceil(groups / 8) * 8 * nchunk workgroups (1-D), block 1024.
+template <int NS, int KMAX, bool GCA>
+__global__ void __launch_bounds__(kThreads) k_soft_agg(SoftArgs a) {
+  constexpr int PR = plane_rows(NS);
+  __shared__ uint32_t s_row[kWaves][NS * 128];
+  __shared__ uint32_t s_seg[kWaves][64];
+  __shared__ uint32_t s_plane[(PR + 1) * 64];
+  __shared__ float s_ex[8];
+
+  const int t = threadIdx.x, lane = t & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+  const int X = a.X, Y = a.Y;
+  const int wg = blockIdx.x, xcd = wg & (kXcds - 1), j = wg / kXcds;
+  const int local = j / a.nchunk, chunk = j - local * a.nchunk;
+  int group = local * kXcds + xcd;
+  if (group >= a.ngroups) return;
+  const int strip = group % a.nstrips;
+  group /= a.nstrips;
+  const int band = group % a.nbands;
+  const int pair = group / a.nbands;
+  const int x0 = strip * kTX;
+  const int ob = (Y + a.nbands - 1) / a.nbands;
+  const int y0 = band * ob, y1 = min(Y, y0 + ob);
+  const int ya = max(0, y0 - a.arm_y), yb = min(Y, y1 + a.arm_y);
+  const int nb = yb - ya, o0 = y0 - ya, o1 = y1 - ya;
+  const int span = a.dhi - a.dlo;
+  const int d0 = a.dlo + (chunk * span) / a.nchunk, d1 = a.dlo + ((chunk + 1) * span) / a.nchunk;
+  const int hx = (a.arm_x + 2) & ~1;
+  const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(a.sp, a.sp_bytes);
+  const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(a.arms, a.arms_bytes);
+  const uint32_t img_l = (uint32_t)(2 * pair), img_r = img_l + 1u;
+  const uint32_t sprow = (uint32_t)a.XS * 8u, armrow = (uint32_t)a.XA * 4u;
+  const float lam_ad = a.lam[0], lam_c = a.lam[1];
+  // e^{-255 |dI| / lambda_AD} = 2^{-|dI| k2}
+  const float k2 = 255.f * 1.4426950408889634f / lam_ad;
+  if (t < 8) s_ex[t] = t < 7 ? fast_exp2(-(float)t * 1.4426950408889634f / lam_c) : 0.f;
+  if (t < 64) s_plane[t] = 0u;
+
+  const int c = lane, x = x0 + lane;
+  const int seg_len = 2 * ((nb + 2 * kWaves - 1) / (2 * kWaves));
+  const int r0 = min(wave * seg_len, nb), r1 = min(r0 + seg_len, nb);
+
+  static_assert(KMAX % 2 == 0, "KMAX must be even");
+  uint32_t marm[KMAX / 2];
+  float se[GCA ? 1 : KMAX], sde[GCA ? 1 : KMAX], isz[GCA ? 1 : KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    uint32_t mn = 0u;
+    const int r = o0 + wave + k * kWaves;
+    const bool in = x < X && r < o1;
+    if (in) mn = a.arms[((size_t)img_l * Y + ya + r) * a.XA + x] >> 16;
+    if (k & 1) marm[k / 2] |= mn << 16;
+    else marm[k / 2] = mn;
+    if constexpr (!GCA) {
+      se[k] = 0.f;
+      sde[k] = 0.f;
+      isz[k] = in ? a.inv_size[((size_t)pair * Y + ya + r) * X + x] * a.zc : 0.f;
+    }
+  }
+  const int fin_base = (o0 + wave + 1) * 64 + c;
+  // byte offset of this lane's first column pair in a padded row
+  const uint32_t vb = (uint32_t)(a.pads + x0 - hx + 2 * lane) * 8u;
+  const uint32_t vx = (uint32_t)x * 4u;
+  const float fx = a.fx;
+  __syncthreads();
+
+  auto cost = [&](uint2 l, uint2 r, int col, int d) -> uint32_t {
+    const float di = fabsf(__uint_as_float(l.x) - __uint_as_float(r.x));
+    const float cf = (2.f - fast_exp2(-di * k2)) - s_ex[__builtin_popcount(l.y ^ r.y)];
+    const uint32_t ci = (uint32_t)(cf * fx + 0.5f);
+    return col - d >= 0 ? ci : (uint32_t)(2.f * fx + 0.5f);
+  };
+
+  for (int d = d0; d < d1; ++d) {
+    const uint32_t vo = vb - (uint32_t)(d * 8);
+    uint32_t run = 0;
+    for (int r = r0; r < r1; ++r) {
+      const uint32_t y = (uint32_t)(ya + r);
+      const uint32_t sl = (img_l * (uint32_t)Y + y) * sprow, sr = (img_r * (uint32_t)Y + y) * sprow;
+      uint32_t carry = 0;
+#pragma unroll
+      for (int s = 0; s < NS; ++s) {
+        const u32x4 L = __builtin_amdgcn_raw_buffer_load_b128(rs, vb + s * 1024, sl, 0);
+        const u32x4 R = __builtin_amdgcn_raw_buffer_load_b128(rs, vo + s * 1024, sr, 0);
+        const int col = x0 - hx + s * 128 + 2 * lane;
+        const uint32_t c0 = cost(make_uint2(L.x, L.y), make_uint2(R.x, R.y), col, d);
+        const uint32_t c1 = cost(make_uint2(L.z, L.w), make_uint2(R.z, R.w), col + 1, d);
+        const uint32_t p = wave_scan_incl(c0 + c1) + carry;
+        if (NS > 1) carry = __builtin_amdgcn_readlane(p, 63);
+        *reinterpret_cast<u32x2*>(&s_row[wave][s * 128 + 2 * lane]) = u32x2{p - c1, p};
+      }
+      const uint32_t am =
+          __builtin_amdgcn_raw_buffer_load_b32(ra, vx, (img_l * (uint32_t)Y + y) * armrow, 0);
+      WAVE_LDS_ORDER();
+      const int m = am & 255u, n = (am >> 8) & 255u;
+      run += s_row[wave][lane + hx + n] - s_row[wave][lane + hx - m - 1];
+      WAVE_LDS_ORDER();
+      s_plane[(r + 1) * 64 + lane] = run;
+    }
+    s_seg[wave][c] = run;
+    __syncthreads();
+    uint32_t off = 0;
+#pragma unroll
+    for (int s = 0; s < kWaves; ++s) {
+      const uint32_t v = s_seg[s][c];
+      off += s < wave ? v : 0u;
+    }
+    if (wave > 0) {
+#pragma unroll 8
+      for (int r = r0; r < r1; ++r) s_plane[(r + 1) * 64 + c] += off;
+    }
+    __syncthreads();
+    const float fd = (float)d;
+#pragma unroll
+    for (int jj = 0; jj < KMAX / 2; ++jj) {
+      uint32_t mj = marm[jj];
+      __asm__ volatile("" : "+v"(mj));
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int k = 2 * jj + h;
+        const int M = (mj >> (16 * h)) & 255u, N = (mj >> (16 * h + 8)) & 255u;
+        const int lo = fin_base - (M + 1) * 64, hi = fin_base + N * 64;
+        const uint32_t ca = s_plane[hi + k * kWaves * 64] - s_plane[lo + k * kWaves * 64];
+        if constexpr (!GCA) {
+          const float e = fast_exp2(-(float)ca * isz[k]);
+          se[k] += e;
+          sde[k] += fd * e;
+        } else {
+          const int r = o0 + wave + k * kWaves;
+          if (x < X && r < o1) {
+            const size_t pix = ((size_t)pair * Y + ya + r) * X + x;
+            const float4 q = a.pc[pix];
+            const float p = fast_exp2(-(float)ca * q.x - q.y);
+            a.gca[(size_t)(d - a.dlo) * a.npair * X * Y + pix] = q.w * p * (fd - q.z);
+          }
+        }
+      }
+    }
+    __syncthreads();
+  }
+
+  if constexpr (!GCA) {
+    if (x < X) {
+      float2* out = a.part + (size_t)(pair * a.nchunk + chunk) * X * Y;
+#pragma unroll
+      for (int k = 0; k < KMAX; ++k) {
+        const int r = o0 + wave + k * kWaves;
+        if (r < o1) out[(size_t)(ya + r) * X + x] = make_float2(se[k], sde[k]);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------- k_soft_merge
+// Sums the chunk partials in chunk order: d_hat = sum d e / sum e and
+// lse2 = log2 sum e.  grid: (ceil(X*Y/256), n), block 256.
+__global__ void __launch_bounds__(256) k_soft_merge(const float2* __restrict__ part, int nchunk,
+                                                    int npix, float* __restrict__ dhat,
+                                                    float* __restrict__ lse2) {
+  const int i = blockIdx.x * 256 + threadIdx.x, pair = blockIdx.y;
+  if (i >= npix) return;
+  const float2* p = part + (size_t)pair * nchunk * npix + i;
+  float s = 0.f, sd = 0.f;
+  for (int c = 0; c < nchunk; ++c) {
+    const float2 v = p[(size_t)c * npix];
+    s += v.x;
+    sd += v.y;
+  }
+  dhat[(size_t)pair * npix + i] = sd / s;
+  lse2[(size_t)pair * npix + i] = __log2f(s);
+}
+
+// ---------------------------------------------------------- k_soft_bprep
+// Per-pixel constants of the adjoint: w = zc / |S| (log2-unit mean per
+// fixed-point aggregate), lse2, d_hat and A = -g_dhat / (tau |S|), so that
+// dL/dCA(d) = A p_d (d - d_hat) with p_d = 2^{-CA w - lse2}.
+// grid: (ceil(X*Y/256), n), block 256.
+__global__ void __launch_bounds__(256) k_soft_bprep(const float* __restrict__ inv_size,
+                                                    const float* __restrict__ lse2,
+                                                    const float* __restrict__ dhat,
+                                                    const float* __restrict__ g_dhat, int npix,
+                                                    float zc, float inv_tau,
+                                                    float4* __restrict__ pc) {
+  const int i = blockIdx.x * 256 + threadIdx.x, pair = blockIdx.y;
+  if (i >= npix) return;
+  const size_t o = (size_t)pair * npix + i;
+  const float is = inv_size[o];
+  pc[o] = make_float4(is * zc, lse2[o], dhat[o], -g_dhat[o] * is * inv_tau);
+}
+
+// ------------------------------------------------------------- k_soft_tr
+// Transposed aggregation of one disparity over a 64-column strip and a band
+// of kSoftBR rows, then the cost derivatives there.
+//   CA(x,y) = sum_{s=-M(x,y)}^{N(x,y)} CA_x(x,y+s)  transposes to
+//   dL/dCA_x(x,y') = sum of dL/dCA(x,y) over the y whose window holds y':
+//   a difference array per column (+g at y - M, -g at y + N + 1), then a
+//   prefix down the column.  Likewise CA_x(x,y) = sum_{t=-m}^{n} C(x+t,y)
+//   transposes to a difference array along the row (+g at x - m, -g at
+//   x + n + 1) and a prefix along it, giving dL/dC.
+// Then with dI = L(x,y) - R(x-d,y), a = 255 |dI|, E = e^{-a/lambda_AD}:
+//   t = dL/dC * dC/d(dI) = dL/dC * (255 / lambda_AD) E sign(dI)
+//   dL/dlambda_AD     += dL/dC * (-E a / lambda_AD^2)
+//   dL/dlambda_census += dL/dC * (-e^{-H/lambda_census} H / lambda_census^2)
+// for x - d >= 0 (the constant cost of x - d < 0 has no derivative).
+// Phase 1: 4 waves = 2 column groups (columns x0 - 32 .. x0 + 95, which hold
+// every column whose horizontal window reaches the strip, arm_x <= 31) x 2
+// halves of the source rows; each lane owns one column of its wave's
+// difference array, so the updates need no atomics.  Phase 2: a wave per
+// band row; its 64 lanes scatter into the row's difference array with LDS
+// atomics (no other wave touches the row) and a DPP scan gives dL/dC.
+struct TrArgs {
+  const float* gca;         // [nds][n][Y][X]
+  const uint32_t* arms;     // [2n][Y][XA]
+  const uint2* sp;          // [2n][Y][XS] padded pixel planes
+  const float* lam;         // device [2]
+  float* t;                 // [nds][n][Y][X]
+  float2* lam_part;         // one {d/dlambda_AD, d/dlambda_census} per workgroup
+  int X, Y, XS, pads, XA, arm_y, npair, dlo, nstrips, nbands;
+};
+
+__global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
+  constexpr int BR = kSoftBR;
+  __shared__ float s_d1[4][BR][64];
+  __shared__ float s_g[BR][128];
+  __shared__ float s_d2[BR][65];
+  __shared__ float2 s_red[4];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int strip = blockIdx.x % a.nstrips, band = blockIdx.x / a.nstrips;
+  const int dj = blockIdx.y, d = a.dlo + dj, pair = blockIdx.z;
+  const int X = a.X, Y = a.Y;
+  const int x0 = strip * 64, y0 = band * BR;
+  const size_t plane = (size_t)X * Y;
+  const float* g = a.gca + ((size_t)dj * a.npair + pair) * plane;
+  const uint32_t* arm = a.arms + (size_t)(2 * pair) * Y * a.XA;
+
+  for (int r = 0; r < BR; ++r) s_d1[wave][r][lane] = 0.f;
+  for (int i = t; i < BR * 65; i += 256) (&s_d2[0][0])[i] = 0.f;
+  // phase 1: column difference arrays
+  {
+    const int cg = wave & 1, rh = wave >> 1;
+    const int col = x0 - 32 + 64 * cg + lane;
+    const bool cv = col >= 0 && col < X;
+    const int ys0 = max(0, y0 - a.arm_y), ys1 = min(Y, y0 + BR + a.arm_y);
+    const int mid = (ys0 + ys1) >> 1;
+    const int ya = rh ? mid : ys0, yb = rh ? ys1 : mid;
+    for (int y = ya; y < yb; ++y) {
+      float gv = 0.f;
+      uint32_t am = 0u;
+      if (cv) {
+        gv = g[(size_t)y * X + col];
+        am = arm[(size_t)y * a.XA + col];
+      }
+      const int lo = y - (int)((am >> 16) & 255u) - y0, hi = y + (int)(am >> 24) + 1 - y0;
+      if (gv != 0.f && hi > 0 && lo < BR) {
+        s_d1[wave][max(lo, 0)][lane] += gv;
+        if (hi < BR) s_d1[wave][hi][lane] -= gv;
+      }
+    }
+  }
+  __syncthreads();
+  if (wave < 2) {
+    float acc = 0.f;
+    for (int r = 0; r < BR; ++r) {
+      acc += s_d1[wave][r][lane] + s_d1[wave + 2][r][lane];
+      s_g[r][64 * wave + lane] = acc;
+    }
+  }
+  __syncthreads();
+  // phase 2: row difference arrays, prefix, cost derivatives
+  const float lam_ad = a.lam[0], lam_c = a.lam[1];
+  const float k2 = 255.f * 1.4426950408889634f / lam_ad;
+  const float kt = 255.f / lam_ad, ka = 1.f / (lam_ad * lam_ad), kc = 1.f / (lam_c * lam_c);
+  const float l2c = 1.4426950408889634f / lam_c;
+  float pa = 0.f, pcs = 0.f;
+  const uint2* spl = a.sp + (size_t)(2 * pair) * Y * a.XS + a.pads;
+  const uint2* spr = a.sp + (size_t)(2 * pair + 1) * Y * a.XS + a.pads;
+  float* tout = a.t + ((size_t)dj * a.npair + pair) * plane;
+  for (int r = wave; r < BR; r += 4) {
+    const int y = y0 + r;
+    if (y >= Y) break;
+#pragma unroll
+    for (int cg = 0; cg < 2; ++cg) {
+      const int col = x0 - 32 + 64 * cg + lane;
+      if (col >= 0 && col < X) {
+        const float gx = s_g[r][64 * cg + lane];
+        const uint32_t am = arm[(size_t)y * a.XA + col];
+        const int lo = col - (int)(am & 255u) - x0, hi = col + (int)((am >> 8) & 255u) + 1 - x0;
+        if (gx != 0.f && hi > 0 && lo < 64) {
+          atomicAdd(&s_d2[r][max(lo, 0)], gx);
+          if (hi < 64) atomicAdd(&s_d2[r][hi], -gx);
+        }
+      }
+    }
+    WAVE_LDS_ORDER();
+    const float gc = wave_scan_incl_f(s_d2[r][lane]);
+    const int x = x0 + lane;
+    if (x < X) {
+      float tv = 0.f;
+      if (x - d >= 0) {
+        const uint2 L = spl[(size_t)y * a.XS + x], R = spr[(size_t)y * a.XS + x - d];
+        const float di = __uint_as_float(L.x) - __uint_as_float(R.x);
+        const float ad = fabsf(di);
+        const float E = fast_exp2(-ad * k2);
+        const float sg = di > 0.f ? 1.f : (di < 0.f ? -1.f : 0.f);
+        tv = gc * kt * E * sg;
+        pa += gc * (-E * 255.f * ad * ka);
+        const int hh = __builtin_popcount(L.y ^ R.y);
+        pcs += gc * (-fast_exp2(-(float)hh * l2c) * (float)hh * kc);
+      }
+      tout[(size_t)y * X + x] = tv;
+    }
+  }
+  // fixed-order reduction of the lambda partials over the workgroup
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    pa += __shfl_down(pa, o);
+    pcs += __shfl_down(pcs, o);
+  }
+  if (lane == 0) s_red[wave] = make_float2(pa, pcs);
+  __syncthreads();
+  if (t == 0) {
+    float2 s = s_red[0];
+    for (int w = 1; w < 4; ++w) { s.x += s_red[w].x; s.y += s_red[w].y; }
+    a.lam_part[((size_t)pair * gridDim.y + dj) * gridDim.x + blockIdx.x] = s;
+  }
+}
+
+// ----------------------------------------------------------- k_soft_gimg
+// dL/d(half image) accumulated over a slab of disparities d = dlo + j:
+//   left  (x,y) += sum_j t_j(x, y)
+//   right (x,y) -= sum_j t_j(x + d_j, y)   (x + d_j < X)
+// grid: (ceil(X/256), Y, n), block 256.
+__global__ void __launch_bounds__(256) k_soft_gimg(const float* __restrict__ t, int nds, int dlo,
+                                                   int npair, int X, int Y,
+                                                   float* __restrict__ g_half) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, pair = blockIdx.z;
+  if (x >= X) return;
+  const size_t plane = (size_t)X * Y;
+  float gl = 0.f, gr = 0.f;
+  for (int j = 0; j < nds; ++j) {
+    const float* tp = t + ((size_t)j * npair + pair) * plane + (size_t)y * X;
+    gl += tp[x];
+    const int xs = x + dlo + j;
+    if (xs < X) gr -= tp[xs];
+  }
+  g_half[(size_t)(2 * pair) * plane + (size_t)y * X + x] += gl;
+  g_half[(size_t)(2 * pair + 1) * plane + (size_t)y * X + x] += gr;
+}
+
+// ---------------------------------------------------------- k_soft_gfull
+// dL/d(RGB) from dL/d(half image): a full-res pixel (u, v) receives g/9 from
+// every half-res pixel whose clamped 3x3 block holds it, once per block cell
+// that lands on it, times the channel's gray weight (77, 150, 29) / 256.
+// grid: (ceil(W/256), H, 2n), block 256.
+__global__ void __launch_bounds__(256) k_soft_gfull(const float* __restrict__ g_half, int W, int H,
+                                                    int X, int Y, float* __restrict__ g_left,
+                                                    float* __restrict__ g_right) {
+  const int u = blockIdx.x * 256 + threadIdx.x, v = blockIdx.y, img = blockIdx.z;
+  if (u >= W) return;
+  const float* gh = g_half + (size_t)img * X * Y;
+  float acc = 0.f;
+  const int yl = max(0, (v - 1) >> 1), yh = min(Y - 1, (v + 2) >> 1);
+  const int xl = max(0, (u - 1) >> 1), xh = min(X - 1, (u + 2) >> 1);
+  for (int y = yl; y <= yh; ++y) {
+    int wy = 0;
+#pragma unroll
+    for (int j = -1; j <= 1; ++j) wy += clampi(2 * y + j, 0, H - 1) == v;
+    if (!wy) continue;
+    for (int x = xl; x <= xh; ++x) {
+      int wx = 0;
+#pragma unroll
+      for (int i = -1; i <= 1; ++i) wx += clampi(2 * x + i, 0, W - 1) == u;
+      if (wx) acc += (float)(wx * wy) * gh[(size_t)y * X + x];
+    }
+  }
+  acc *= 1.f / (9.f * 256.f);
+  float* out = ((img & 1) ? g_right : g_left) + ((size_t)(img >> 1) * H * W + (size_t)v * W + u) * 3;
+  out[0] = 77.f * acc;
+  out[1] = 150.f * acc;
+  out[2] = 29.f * acc;
+}
+
+// ------------------------------------------------------------ k_soft_lam
+// Sum of the per-workgroup lambda partials in a fixed order.
+// grid: 1, block 256.
+__global__ void __launch_bounds__(256) k_soft_lam(const float2* __restrict__ part, int count,
+                                                  float* __restrict__ g_lam) {
+  __shared__ float2 s[256];
+  const int t = threadIdx.x;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int i = t; i < count; i += 256) {
+    acc.x += part[i].x;
+    acc.y += part[i].y;
+  }
+  s[t] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      s[t].x += s[t + o].x;
+      s[t].y += s[t + o].y;
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    g_lam[0] = s[0].x;
+    g_lam[1] = s[0].y;
+  }
+}
+
+// ----------------------------------------------------------- k_fill_f32
+__global__ void k_fill_f32(float* __restrict__ p, size_t n, float v) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+// ---------------------------------------------------------------- k_l1_*
+// L = (1/n) sum over pairs of mean over {(x,y): nonocc(2x,2y)} of
+// |2 d_hat(x,y) - GT(2x,2y)|; dL/dd_hat = 2 sign(2 d_hat - GT) / (n count)
+// there (sign(0) = 0), 0 elsewhere.
+// k_l1_partial grid: (nblk, n), block 256; partial sums per block.
+__global__ void __launch_bounds__(256) k_l1_partial(const float* __restrict__ dhat,
+                                                    const int16_t* __restrict__ gt,
+                                                    const uint8_t* __restrict__ nonocc, int W,
+                                                    int H, int X, int Y,
+                                                    float2* __restrict__ part) {
+  __shared__ float2 s[256];
+  const int t = threadIdx.x, pair = blockIdx.y;
+  const int npix = X * Y;
+  float sum = 0.f, cnt = 0.f;
+  for (int i = blockIdx.x * 256 + t; i < npix; i += gridDim.x * 256) {
+    const int y = i / X, x = i - y * X;
+    const size_t f = (size_t)pair * H * W + (size_t)(2 * y) * W + 2 * x;
+    if (nonocc[f]) {
+      sum += fabsf(2.f * dhat[(size_t)pair * npix + i] - (float)gt[f]);
+      cnt += 1.f;
+    }
+  }
+  s[t] = make_float2(sum, cnt);
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (t < o) {
+      s[t].x += s[t + o].x;
+      s[t].y += s[t + o].y;
+    }
+    __syncthreads();
+  }
+  if (t == 0) part[(size_t)pair * gridDim.x + blockIdx.x] = s[0];
+}
+
+// k_l1_final grid: 1, block 64: loss and the per-pair counts.
+__global__ void __launch_bounds__(64) k_l1_final(const float2* __restrict__ part, int nblk,
+                                                 int npair, float* __restrict__ loss,
+                                                 float* __restrict__ counts) {
+  if (threadIdx.x != 0) return;
+  float total = 0.f;
+  for (int p = 0; p < npair; ++p) {
+    float s = 0.f, c = 0.f;
+    for (int b = 0; b < nblk; ++b) {
+      s += part[(size_t)p * nblk + b].x;
+      c += part[(size_t)p * nblk + b].y;
+    }
+    counts[p] = c;
+    total += s / fmaxf(c, 1.f);
+  }
+  *loss = total / (float)npair;
+}
+
+// k_l1_grad grid: (ceil(X*Y/256), n), block 256.
+__global__ void __launch_bounds__(256) k_l1_grad(const float* __restrict__ dhat,
+                                                 const int16_t* __restrict__ gt,
+                                                 const uint8_t* __restrict__ nonocc,
+                                                 const float* __restrict__ counts,
+                                                 const float* __restrict__ gscale, int W, int H,
+                                                 int X, int Y, int npair,
+                                                 float* __restrict__ g_dhat) {
+  const int i = blockIdx.x * 256 + threadIdx.x, pair = blockIdx.y;
+  const int npix = X * Y;
+  if (i >= npix) return;
+  const int y = i / X, x = i - y * X;
+  const size_t f = (size_t)pair * H * W + (size_t)(2 * y) * W + 2 * x;
+  float g = 0.f;
+  if (nonocc[f]) {
+    const float r = 2.f * dhat[(size_t)pair * npix + i] - (float)gt[f];
+    const float sg = r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f);
+    g = 2.f * sg / (fmaxf(counts[pair], 1.f) * (float)npair);
+    if (gscale) g *= *gscale;
+  }
+  g_dhat[(size_t)pair * npix + i] = g;
+}
+
+}  // namespace
+}  // namespace stereo_dev

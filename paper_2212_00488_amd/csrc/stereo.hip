@@ -12,11 +12,13 @@
 #include <string>
 #include <vector>
 
+#include "context.h"
 #include "kernels.hip.h"
+#include "pipeline.h"
 
 using namespace stereo_dev;
 
-namespace {
+namespace stereo_host {
 
 // Cost tables of Eq. 4 and Eq. 5 in fixed point: S(1 - exp(-t)) rounded half
 // up, with t = (a / 255) / lambda_AD for brightness difference a and
@@ -27,34 +29,6 @@ void build_tables(const stereo_params& p, uint16_t ad[256], uint16_t mc[7]) {
   for (int h = 0; h < 7; ++h) mc[h] = (uint16_t)std::floor(S * (1.0 - std::exp(-h / lmc)) + 0.5);
 }
 
-struct Plan {
-  int W = 0, H = 0, Dmax = 0, X = 0, Y = 0, D = 0, npair = 0;
-  stereo_params p{};
-  uint16_t lut_ad[256]{}, lut_mc[7]{};
-  int cmax = 0;
-  int ns = 1, kmax = 8, nstrips = 0, nbands = 0, nchunk = 0;
-  int XP = 0, pad = 0, XA = 0;  // padded pitches of pk and arms
-  int nk = 0;                   // padded plane stride of keys, disp and mincost
-  size_t bytes = 0;
-  // device memory, one block carved into planes
-  void* block = nullptr;
-  uint8_t* half = nullptr;    // [2*npair][Y][X]
-  uint32_t* pk = nullptr;     // [2*npair][Y][XP]  gray*2 | census<<16, kSentinel padding
-  uint32_t* arms = nullptr;   // [2*npair][Y][XA]  zero padding
-  uint16_t* tab = nullptr;    // [7][512]
-  uint32_t* keys = nullptr;   // [npair][nchunk][2][Y][X]
-  int16_t* disp = nullptr;    // [2*npair][Y][X]
-  uint32_t* mincost = nullptr;// [2*npair][Y][X]
-  uint8_t* gcp = nullptr;     // [npair][Y][X]
-  int16_t* med = nullptr;     // [npair][Y][X]
-  int16_t* filled = nullptr;  // [npair][Y][X]
-  // debug planes, allocated on demand
-  void* dbg_block = nullptr;
-  uint16_t* dbg_cost = nullptr;
-  uint32_t* dbg_cax = nullptr;
-  uint32_t* dbg_ca = nullptr;
-  uint64_t last_use = 0;
-};
 
 bool same_params(const stereo_params& a, const stereo_params& b) {
   return a.lambda_ad == b.lambda_ad && a.lambda_mc == b.lambda_mc && a.cost_scale == b.cost_scale &&
@@ -62,38 +36,9 @@ bool same_params(const stereo_params& a, const stereo_params& b) {
          a.fill_T == b.fill_T;
 }
 
-}  // namespace
+}  // namespace stereo_host
 
-struct stereo_ctx {
-  int device = 0;
-  // stage timing: one set of STEREO_NUM_STAGES + 1 events per timed call
-  std::vector<hipEvent_t> events;
-  int timed_calls = 0;
-  int num_cu = 256;
-  size_t mem_cap = 0, used = 0;
-  std::vector<Plan*> plans;
-  std::string err;
-  Plan* last = nullptr;  // plan of the last call that kept its intermediates
-  uint64_t tick = 0;
-};
-
-namespace {
-
-int fail(stereo_ctx* c, int code, const char* fmt, ...) {
-  char buf[512];
-  va_list ap;
-  va_start(ap, fmt);
-  vsnprintf(buf, sizeof buf, fmt, ap);
-  va_end(ap);
-  if (c) c->err = buf;
-  return code;
-}
-
-#define HIP_TRY(ctx, call)                                                              \
-  do {                                                                                  \
-    hipError_t e_ = (call);                                                             \
-    if (e_ != hipSuccess) return fail(ctx, STEREO_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
-  } while (0)
+namespace stereo_host {
 
 int check_params(stereo_ctx* c, const stereo_params& p) {
   if (p.size != sizeof(stereo_params))
@@ -124,12 +69,6 @@ void free_plan(Plan* pl) {
   delete pl;
 }
 
-template <class T>
-T* carve(char*& cur, size_t count) {
-  T* p = reinterpret_cast<T*>(cur);
-  cur += (count * sizeof(T) + 255) & ~size_t(255);
-  return p;
-}
 
 // Launch geometry: bands keep the k_match LDS plane and the per-thread key
 // registers within bounds; d-chunks raise the workgroup count to fill the CUs.
@@ -235,9 +174,11 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
   return 0;
 }
 
-int get_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int npair, Plan** out) {
+int get_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int npair,
+             const void* owner, Plan** out) {
   for (Plan* pl : c->plans)
-    if (pl->W == W && pl->H == H && pl->Dmax == Dmax && pl->npair >= npair && same_params(pl->p, p)) {
+    if (pl->W == W && pl->H == H && pl->Dmax == Dmax && pl->npair >= npair && pl->owner == owner &&
+        same_params(pl->p, p)) {
       pl->last_use = ++c->tick;
       *out = pl;
       return 0;
@@ -259,6 +200,7 @@ int get_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int 
   }
   if (rc) return rc;
   pl->last_use = ++c->tick;
+  pl->owner = owner;
   c->plans.push_back(pl);
   *out = pl;
   return 0;
@@ -364,7 +306,9 @@ int common_checks(stereo_ctx* c, int W, int H, int Dmax, const stereo_params* pa
   return check_params(c, *p);
 }
 
-}  // namespace
+}  // namespace stereo_host
+
+using namespace stereo_host;
 
 extern "C" {
 
@@ -407,6 +351,8 @@ void stereo_destroy(stereo_ctx* c) {
   (void)hipSetDevice(c->device);
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   for (Plan* pl : c->plans) free_plan(pl);
+  free_soft_plans(c->soft_plans);
+  if (c->l1_block) (void)hipFree(c->l1_block);
   delete c;
 }
 
@@ -427,7 +373,7 @@ int stereo_disparity_batch(stereo_ctx* c, const uint8_t* const* left, const uint
   const bool keep = (p.flags & STEREO_F_KEEP_INTERMEDIATES) != 0;
   const int per = std::min(n, kMaxPairs);
   Plan* pl = nullptr;
-  rc = get_plan(c, W, H, Dmax, p, per, &pl);
+  rc = get_plan(c, W, H, Dmax, p, per, stream, &pl);
   if (rc) return rc;
   for (int i0 = 0; i0 < n; i0 += kMaxPairs) {
     const int m = std::min(kMaxPairs, n - i0);

@@ -1,0 +1,63 @@
+"""torch.autograd front end of the soft-argmin head (include/stereo.h,
+stereo_soft_*).  Forward and backward both run in the library's kernels;
+these classes only route tensors and the upstream gradient.
+
+    ctx = Stereo(0)
+    d_hat = soft_disparity(ctx, left, right, lambdas, dmax)        # [n][Y][X]
+    loss = l1_loss(ctx, d_hat, gt, nonocc)                          # [1]
+    loss.backward()   # gradients in left.grad, right.grad, lambdas.grad
+
+left, right: float32 [n][H][W][3] in [0, 1] on the device; lambdas: float32
+[2] = (lambda_AD, lambda_census) on the device; gt: int16 [n][H][W]; nonocc:
+uint8 [n][H][W].
+"""
+
+from __future__ import annotations
+
+import torch
+
+from .binding import SoftParams
+
+
+class SoftArgmin(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, left, right, lambdas, dmax, params, stereo):
+        left, right, lambdas = left.contiguous(), right.contiguous(), lambdas.contiguous()
+        d_hat, lse2 = stereo.soft_forward(left, right, lambdas, dmax, params)
+        fctx.save_for_backward(left, right, lambdas, d_hat, lse2)
+        fctx.dmax, fctx.params, fctx.stereo = dmax, params, stereo
+        fctx.mark_non_differentiable(lse2)
+        return d_hat, lse2
+
+    @staticmethod
+    def backward(fctx, g_dhat, _g_lse):
+        left, right, lambdas, d_hat, lse2 = fctx.saved_tensors
+        g_left, g_right, g_lam = fctx.stereo.soft_backward(
+            left, right, lambdas, fctx.dmax, d_hat, lse2, g_dhat.contiguous(), fctx.params)
+        return g_left, g_right, g_lam, None, None, None
+
+
+class L1Loss(torch.autograd.Function):
+    @staticmethod
+    def forward(fctx, d_hat, gt, nonocc, stereo):
+        d_hat = d_hat.contiguous()
+        fctx.save_for_backward(d_hat, gt, nonocc)
+        fctx.stereo = stereo
+        return stereo.l1_loss(d_hat, gt, nonocc)
+
+    @staticmethod
+    def backward(fctx, g_loss):
+        d_hat, gt, nonocc = fctx.saved_tensors
+        g = fctx.stereo.l1_grad(d_hat, gt, nonocc, g_loss.contiguous().to(torch.float32))
+        return g, None, None, None
+
+
+def soft_disparity(stereo, left, right, lambdas, dmax: int, params: SoftParams | None = None):
+    """Half-resolution soft-argmin disparity [n][Y][X] (differentiable)."""
+    d_hat, _ = SoftArgmin.apply(left, right, lambdas, dmax, params, stereo)
+    return d_hat
+
+
+def l1_loss(stereo, d_hat, gt, nonocc):
+    """Mean over pairs of the mean |2 d_hat - GT(2x,2y)| on non-occluded pixels."""
+    return L1Loss.apply(d_hat, gt, nonocc, stereo)

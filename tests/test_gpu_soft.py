@@ -1,0 +1,193 @@
+"""GPU parity of the soft-argmin head against the FP64 oracle (oracle/soft.py).
+
+Tolerances follow from the kernel's arithmetic: costs enter the aggregate in
+fixed point with 2^-19 resolution (k = 18 for the default arms), so the mean
+cost is within 2^-19 of the exact one and a logit (mean / tau) within
+2e-5; the rest is float32 (relative 1e-6 per operation).  d_hat is compared
+to 1e-3 absolute, the loss to 1e-4 relative and every gradient to 1e-3
+relative to its largest magnitude (and in norm).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import soft as osoft
+from paper_2212_00488_amd import Stereo
+from paper_2212_00488_amd.binding import soft_default_params
+from paper_2212_00488_amd.soft import l1_loss, soft_disparity
+from paper_2212_00488_amd.synth import make_pair
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda:0")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    c = Stereo(0)
+    yield c
+    c.close()
+
+
+def float_pairs(n, W, H, dmax, seed, noise=0.0):
+    """n synthetic pairs as float32 [0,1] images (plus GT and mask); noise
+    adds small uniform jitter so that no two intensities tie exactly."""
+    rng = np.random.default_rng(seed)
+    L, R, G, M = [], [], [], []
+    for i in range(n):
+        p = make_pair(W, H, dmax, segments=4, seed=seed + i)
+        l = p.left.astype(np.float32) / np.float32(255.0)
+        r = p.right.astype(np.float32) / np.float32(255.0)
+        if noise:
+            l = np.clip(l + rng.uniform(-noise, noise, l.shape).astype(np.float32), 0, 1)
+            r = np.clip(r + rng.uniform(-noise, noise, r.shape).astype(np.float32), 0, 1)
+        L.append(l.astype(np.float32))
+        R.append(r.astype(np.float32))
+        G.append(p.gt)
+        M.append(p.nonocc)
+    return np.stack(L), np.stack(R), np.stack(G), np.stack(M)
+
+
+def to_dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a)).to(DEV)
+    return t.to(dtype) if dtype is not None else t
+
+
+def sp_from(p: osoft.SoftParams):
+    return soft_default_params(tau=p.tau, color_delta=p.color_delta, arm_x=p.arm_x,
+                               arm_y=p.arm_y)
+
+
+def run_gpu(ctx, L, R, G, M, dmax, p, lam=None):
+    lam = lam if lam is not None else (p.lambda_ad, p.lambda_census)
+    left = to_dev(L).requires_grad_(True)
+    right = to_dev(R).requires_grad_(True)
+    lambdas = torch.tensor(lam, dtype=torch.float32, device=DEV, requires_grad=True)
+    d_hat = soft_disparity(ctx, left, right, lambdas, dmax, sp_from(p))
+    loss = l1_loss(ctx, d_hat, to_dev(G.astype(np.int16)), to_dev(M.astype(np.uint8)))
+    loss.backward()
+    torch.cuda.synchronize()
+    return (d_hat.detach().cpu().numpy(), float(loss.detach().cpu()[0]),
+            left.grad.cpu().numpy(), right.grad.cpu().numpy(), lambdas.grad.cpu().numpy())
+
+
+def oracle_dhat(L, R, dmax, p):
+    out = []
+    for i in range(len(L)):
+        r = osoft.forward(torch.tensor(L[i], dtype=torch.float64),
+                          torch.tensor(R[i], dtype=torch.float64), dmax,
+                          torch.tensor(p.lambda_ad, dtype=torch.float64),
+                          torch.tensor(p.lambda_census, dtype=torch.float64), p)
+        out.append(r["d_hat"].numpy())
+    return np.stack(out)
+
+
+def assert_grad_close(g, r, name, rel=1e-3):
+    scale = float(np.abs(r).max())
+    assert scale > 0, name
+    err = float(np.abs(g - r).max())
+    assert err <= rel * scale, f"{name}: max err {err:.3e} vs {rel} x {scale:.3e}"
+    nerr = float(np.linalg.norm((g - r).ravel()) / np.linalg.norm(r.ravel()))
+    assert nerr <= rel, f"{name}: norm rel err {nerr:.3e}"
+
+
+@pytest.mark.parametrize("case", [
+    dict(W=64, H=48, dmax=32, n=2, seed=500),          # the FD configuration (D = 16)
+    dict(W=67, H=41, dmax=20, n=1, seed=510),          # odd sizes, ragged strip and band
+    dict(W=150, H=30, dmax=40, n=3, seed=520),         # three strips
+])
+def test_forward_loss_and_gradients_match_oracle(ctx, case):
+    W, H, dmax, n, seed = case["W"], case["H"], case["dmax"], case["n"], case["seed"]
+    L, R, G, M = float_pairs(n, W, H, dmax, seed, noise=0.002)
+    p = osoft.SoftParams()
+    d_hat, loss, gl, gr, glam = run_gpu(ctx, L, R, G, M, dmax, p)
+    ref = oracle_dhat(L, R, dmax, p)
+    assert np.all(np.isfinite(d_hat))
+    assert float(np.abs(d_hat - ref).max()) <= 1e-3
+    rloss, rgl, rgr, rglam = osoft.loss_and_grads(list(L), list(R), list(G), list(M), dmax, p)
+    assert abs(loss - rloss) <= 1e-4 * abs(rloss)
+    assert_grad_close(gl, rgl, "g_left")
+    assert_grad_close(gr, rgr, "g_right")
+    for k in range(2):
+        assert abs(glam[k] - rglam[k]) <= 1e-3 * abs(rglam[k]), (k, glam, rglam)
+
+
+def test_arm_and_temperature_variants_match_oracle(ctx):
+    L, R, G, M = float_pairs(1, 70, 36, 24, 530, noise=0.002)
+    for p in (osoft.SoftParams(tau=0.3, arm_x=5, arm_y=4, color_delta=30),
+              osoft.SoftParams(tau=0.05, arm_x=31, arm_y=63),
+              osoft.SoftParams(arm_x=0, arm_y=0)):
+        d_hat, loss, gl, gr, glam = run_gpu(ctx, L, R, G, M, 24, p)
+        ref = oracle_dhat(L, R, 24, p)
+        assert float(np.abs(d_hat - ref).max()) <= 1e-3, p
+        rloss, rgl, rgr, rglam = osoft.loss_and_grads(list(L), list(R), list(G), list(M), 24, p)
+        assert_grad_close(gl, rgl, f"g_left {p}")
+        assert_grad_close(gr, rgr, f"g_right {p}")
+        for k in range(2):
+            assert abs(glam[k] - rglam[k]) <= 1e-3 * abs(rglam[k]) + 1e-9, (p, k, glam, rglam)
+
+
+def test_lambda_gradient_matches_gpu_central_differences(ctx):
+    """Central differences of the GPU loss itself (float32, so a relative
+    step of 1e-2 and a tolerance of 2e-3)."""
+    L, R, G, M = float_pairs(2, 64, 48, 32, 540, noise=0.002)
+    p = osoft.SoftParams()
+    _, _, _, _, glam = run_gpu(ctx, L, R, G, M, 32, p)
+    base = np.array([p.lambda_ad, p.lambda_census])
+    for k in range(2):
+        h = 1e-2 * base[k]
+        vals = []
+        for sgn in (1, -1):
+            lam = base.copy()
+            lam[k] += sgn * h
+            with torch.no_grad():
+                lt = torch.tensor(lam, dtype=torch.float32, device=DEV)
+                d = soft_disparity(ctx, to_dev(L), to_dev(R), lt, 32, sp_from(p))
+                vals.append(float(l1_loss(ctx, d, to_dev(G.astype(np.int16)),
+                                          to_dev(M.astype(np.uint8))).cpu()[0]))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        assert abs(fd - glam[k]) <= 2e-3 * abs(glam[k]) + 1e-7, (k, fd, glam[k])
+
+
+def test_backward_is_deterministic_and_batch_matches_single(ctx):
+    L, R, G, M = float_pairs(3, 96, 40, 30, 550, noise=0.002)
+    p = osoft.SoftParams()
+    a = run_gpu(ctx, L, R, G, M, 30, p)
+    b = run_gpu(ctx, L, R, G, M, 30, p)
+    for u, v in zip(a, b):
+        assert np.array_equal(np.asarray(u), np.asarray(v))
+    # pair 1 alone: same d_hat (chunk sums may group differently) and, with the
+    # loss of one pair instead of the mean of three, 3x the image gradients
+    s = run_gpu(ctx, L[1:2], R[1:2], G[1:2], M[1:2], 30, p)
+    assert float(np.abs(s[0][0] - a[0][1]).max()) <= 1e-5
+    assert_grad_close(s[2][0], 3.0 * a[2][1], "single vs batch g_left", rel=1e-4)
+
+
+def test_paper_size_batch_rows_match_oracle(ctx):
+    """4 x 1436x992, Dmax = 145 (the differentiable configuration): d_hat of
+    a band of rows against the oracle run on a crop of rows wide enough that
+    the band's features, windows and borders are those of the full image."""
+    W, H, dmax = 1436, 992, 145
+    L, R, G, M = float_pairs(4, W, H, dmax, 400)
+    p = osoft.SoftParams()
+    lambdas = torch.tensor([p.lambda_ad, p.lambda_census], dtype=torch.float32, device=DEV,
+                           requires_grad=True)
+    left = to_dev(L).requires_grad_(True)
+    right = to_dev(R).requires_grad_(True)
+    d_hat = soft_disparity(ctx, left, right, lambdas, dmax, sp_from(p))
+    loss = l1_loss(ctx, d_hat, to_dev(G.astype(np.int16)), to_dev(M.astype(np.uint8)))
+    loss.backward()
+    torch.cuda.synchronize()
+    dh = d_hat.detach().cpu().numpy()
+    assert np.all(np.isfinite(dh)) and dh.min() >= 0 and dh.max() <= 72
+    assert np.all(np.isfinite(left.grad.cpu().numpy()))
+    assert np.all(np.isfinite(right.grad.cpu().numpy()))
+    assert np.all(np.isfinite(lambdas.grad.cpu().numpy()))
+    y0, y1 = 240, 256                    # half-res rows checked (band boundary at 248)
+    ya, yb = y0 - 36, y1 + 36            # crop in half-res rows
+    for i in (0, 3):
+        Lc = L[i, 2 * ya:2 * yb]
+        Rc = R[i, 2 * ya:2 * yb]
+        ref = oracle_dhat(Lc[None], Rc[None], dmax, p)[0]
+        got = dh[i, y0:y1]
+        assert float(np.abs(got - ref[y0 - ya:y1 - ya]).max()) <= 1e-3
