@@ -59,9 +59,9 @@ def lib():
             "or_wta": [P, P, P, P, P, P, I, I, I, P, P, P, P, P, P],
             "or_crosscheck": [P, P, I, I, P],
             "or_median": [P, I, I, P],
-            "or_fill": [P, P, P, I, I, I, P],
+            "or_fill": [P, P, P, I, I, I, I, P],
             "or_upscale": [P, P, I, I, I, P],
-            "or_disparity": [P, P, I, I, I, Dd, Dd, I, I, I, I, I, P] + [P] * 13,
+            "or_disparity": [P, P, I, I, I, Dd, Dd, I, I, I, I, I, I, I, I, P] + [P] * 13,
             "or_num_threads": [],
         }
         for name, args in sig.items():
@@ -81,6 +81,12 @@ class Params:
     arm_x: int = 21
     arm_y: int = 31
     fill_T: int = 3
+    arm_x_r: int = -1     # horizontal arm cap of the right image; -1: arm_x
+    fill_mode: int = 0    # 0 bilateral (Sec. III-E), 1 closer GCP, 2 smaller disparity
+    full_res: bool = False  # the method on the original images (no down/upscale)
+
+    def cap_r(self) -> int:
+        return self.arm_x if self.arm_x_r < 0 else self.arm_x_r
 
 
 def _p(a: np.ndarray):
@@ -203,11 +209,11 @@ def median(d):
     return m
 
 
-def fill(med, gcp, hl, T=3):
+def fill(med, gcp, hl, T=3, mode=0):
     med, gcp, hl = _c(med, np.int16), _c(gcp, np.uint8), _c(hl, np.uint8)
     Y, X = med.shape
     out = np.zeros((Y, X), np.int16)
-    lib().or_fill(_p(med), _p(gcp), _p(hl), X, Y, int(T), _p(out))
+    lib().or_fill(_p(med), _p(gcp), _p(hl), X, Y, int(T), int(mode), _p(out))
     return out
 
 
@@ -223,7 +229,7 @@ def disparity(left, right, dmax, p: Params = Params()):
     """Whole pipeline; returns a dict with the output and every intermediate."""
     left, right = _c(left, np.uint8), _c(right, np.uint8)
     H, W, _ = left.shape
-    X, Y = half_size(W, H)
+    X, Y = (W, H) if p.full_res else half_size(W, H)
     r = {
         "out": np.zeros((H, W), np.int16),
         "half_l": np.zeros((Y, X), np.uint8), "half_r": np.zeros((Y, X), np.uint8),
@@ -238,6 +244,7 @@ def disparity(left, right, dmax, p: Params = Params()):
             "disp_r", "min_l", "min_r", "gcp", "median", "filled"]
     rc = lib().or_disparity(_p(left), _p(right), W, H, int(dmax), p.lambda_ad, p.lambda_mc,
                             p.cost_scale, p.color_delta, p.arm_x, p.arm_y, p.fill_T,
+                            p.cap_r(), p.fill_mode, int(p.full_res),
                             _p(r["out"]), *[_p(r[k]) for k in keys])
     if rc:
         raise ValueError(f"oracle or_disparity failed ({rc})")

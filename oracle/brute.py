@@ -146,7 +146,9 @@ def median(d):
              for x in range(X)] for y in range(Y)]
 
 
-def fill(med, gcp, hl, T):
+def fill(med, gcp, hl, T, mode=0):
+    """mode 0: the bilateral rule; 1: the GCP nearer in distance (ties to
+    the right); 2: the smaller disparity of the two."""
     Y, X = len(med), len(med[0])
     out = [[0] * X for _ in range(Y)]
     for y in range(Y):
@@ -161,7 +163,11 @@ def fill(med, gcp, hl, T):
                 xl, xr = left[-1], right[0]
                 i, j = x - xl, xr - x
                 a, b = med[y][xl], med[y][xr]
-                if abs(a - b) <= T:
+                if mode == 1:
+                    out[y][x] = min((i, 1, a), (j, 0, b))[2]  # equal distance: right
+                elif mode == 2:
+                    out[y][x] = min(a, b)
+                elif abs(a - b) <= T:
                     # a + i (b - a) / (i + j), rounded half up, in exact rationals
                     out[y][x] = math.floor(Fraction(a) + Fraction(i * (b - a), i + j)
                                            + Fraction(1, 2))
@@ -203,19 +209,25 @@ def upscale(dp, gfull, T):
     return out
 
 
-def disparity(left, right, dmax, lambda_ad, lambda_mc, S, delta, ax, ay, T):
-    """Whole path on nested lists; returns a dict of every intermediate."""
+def disparity(left, right, dmax, lambda_ad, lambda_mc, S, delta, ax, ay, T, ax_r=None,
+              fill_mode=0, full_res=False):
+    """Whole path on nested lists; returns a dict of every intermediate.
+    ax_r: horizontal cap of the right image (None: ax); full_res: the method
+    on the original images, whole range, no upscale."""
     tad, tmc = tables(lambda_ad, lambda_mc, S)
     gl, gr = gray(left), gray(right)
-    hl, hr = downscale(gl), downscale(gr)
+    if full_res:
+        hl, hr = [row[:] for row in gl], [row[:] for row in gr]
+    else:
+        hl, hr = downscale(gl), downscale(gr)
     cl, cr = census(hl), census(hr)
-    al, ar = arms(hl, delta, ax, ay), arms(hr, delta, ax, ay)
-    D = (dmax + 1) // 2
+    al, ar = arms(hl, delta, ax, ay), arms(hr, delta, ax if ax_r is None else ax_r, ay)
+    D = dmax if full_res else (dmax + 1) // 2
     dl, dr, ml, mr = wta(hl, hr, cl, cr, al, ar, D, tad, tmc)
     g = crosscheck(dl, dr)
     md = median(dl)
-    fl = fill(md, g, hl, T)
-    out = upscale(fl, gl, T)
+    fl = fill(md, g, hl, T, fill_mode)
+    out = [row[:] for row in fl] if full_res else upscale(fl, gl, T)
     return dict(tables=(tad, tmc), gray_l=gl, half_l=hl, half_r=hr, census_l=cl, census_r=cr,
                 arms_l=al, arms_r=ar, disp_l=dl, disp_r=dr, min_l=ml, min_r=mr, gcp=g,
                 median=md, filled=fl, out=out)

@@ -29,6 +29,13 @@
  *             floor division; ties of the colour test go right   (Sec. III-E, Eq. 11)
  *   upscale   x2 disparity; odd columns by the bilateral rule on full-res
  *             gray; odd rows the rounded-up mean                  (Step8)
+ * Variants of Sec. III-E and Sec. V:
+ *   fill mode 1: the GCP closer in distance (the right one at equal
+ *             distance); mode 2: the smaller of the two disparities; one
+ *             side only: copy it; none: 0                         (Sec. III-E)
+ *   arm_x_r   horizontal arm cap of the right image, W_y common    (Sec. V)
+ *   full_res  no downscale and no upscale: the method on the original
+ *             images over the whole range [0, Dmax-1]            (Sec. V)
  *
  * Parity status of each function is stated in its comment.
  */
@@ -292,7 +299,7 @@ void or_median(const int16_t* din, int X, int Y, int16_t* out) {
  * tie.  One side only: copy it.  No GCP in the row: 0.
  * Pinned: all-GCP map, linear ramp, step edge, brute force. */
 void or_fill(const int16_t* med, const uint8_t* gcp, const uint8_t* hl,
-             int X, int Y, int T, int16_t* out) {
+             int X, int Y, int T, int mode, int16_t* out) {
   for (int y = 0; y < Y; ++y)
     for (int x = 0; x < X; ++x) {
       size_t r = (size_t)y * X;
@@ -301,7 +308,12 @@ void or_fill(const int16_t* med, const uint8_t* gcp, const uint8_t* hl,
       while (x - i >= 0 && !gcp[r + x - i]) ++i;
       while (x + j < X && !gcp[r + x + j]) ++j;
       int hasl = x - i >= 0, hasr = x + j < X, v;
-      if (hasl && hasr) {
+      if (hasl && hasr && mode == 1) {
+        v = i < j ? med[r + x - i] : med[r + x + j];
+      } else if (hasl && hasr && mode == 2) {
+        int dlv = med[r + x - i], drv = med[r + x + j];
+        v = dlv < drv ? dlv : drv;
+      } else if (hasl && hasr) {
         int dlv = med[r + x - i], drv = med[r + x + j];
         if (absi(dlv - drv) <= T) {
           v = dlv + floordiv(2 * i * (drv - dlv) + (i + j), 2 * (i + j));
@@ -372,13 +384,15 @@ void or_upscale(const int16_t* dp, const uint8_t* gfull, int W, int H, int T, in
  * -2 on allocation failure. */
 int or_disparity(const uint8_t* left_rgb, const uint8_t* right_rgb, int W, int H, int Dmax,
                  double lambda_ad, double lambda_mc, int S, int delta, int arm_x, int arm_y,
-                 int T, int16_t* out,
+                 int T, int arm_x_r, int fill_mode, int full_res, int16_t* out,
                  uint8_t* o_half_l, uint8_t* o_half_r, uint8_t* o_census_l, uint8_t* o_census_r,
                  uint8_t* o_arms_l, uint8_t* o_arms_r, int16_t* o_disp_l, int16_t* o_disp_r,
                  uint32_t* o_min_l, uint32_t* o_min_r, uint8_t* o_gcp, int16_t* o_median,
                  int16_t* o_filled) {
   if (W < 2 || H < 2 || Dmax < 1) return -1;
-  int X = (W + 1) / 2, Y = (H + 1) / 2, D = (Dmax + 1) / 2;
+  /* full resolution: no downscale (K = 1), the whole disparity range, no upscale */
+  int X = full_res ? W : (W + 1) / 2, Y = full_res ? H : (H + 1) / 2;
+  int D = full_res ? Dmax : (Dmax + 1) / 2;
   size_t nf = (size_t)W * H, nh = (size_t)X * Y;
   uint16_t lut_ad[256], lut_mc[7];
   or_lut(lambda_ad, lambda_mc, S, lut_ad, lut_mc);
@@ -400,18 +414,26 @@ int or_disparity(const uint8_t* left_rgb, const uint8_t* right_rgb, int W, int H
     goto done;
   or_gray(left_rgb, W, H, gl);
   or_gray(right_rgb, W, H, gr);
-  or_downscale(gl, W, H, hl);
-  or_downscale(gr, W, H, hr);
+  if (full_res) {
+    memcpy(hl, gl, nh);
+    memcpy(hr, gr, nh);
+  } else {
+    or_downscale(gl, W, H, hl);
+    or_downscale(gr, W, H, hr);
+  }
   or_census(hl, X, Y, cl);
   or_census(hr, X, Y, cr);
   or_arms(hl, X, Y, delta, arm_x, arm_y, al);
-  or_arms(hr, X, Y, delta, arm_x, arm_y, ar);
+  or_arms(hr, X, Y, delta, arm_x_r, arm_y, ar);
   rc = or_wta(hl, hr, cl, cr, al, ar, X, Y, D, lut_ad, lut_mc, dl, dr, o_min_l, o_min_r);
   if (rc) goto done;
   or_crosscheck(dl, dr, X, Y, gc);
   or_median(dl, X, Y, md);
-  or_fill(md, gc, hl, X, Y, T, fl);
-  or_upscale(fl, gl, W, H, T, out);
+  or_fill(md, gc, hl, X, Y, T, fill_mode, fl);
+  if (full_res)
+    memcpy(out, fl, nh * 2);
+  else
+    or_upscale(fl, gl, W, H, T, out);
   if (o_half_l) memcpy(o_half_l, hl, nh);
   if (o_half_r) memcpy(o_half_r, hr, nh);
   if (o_census_l) memcpy(o_census_l, cl, nh);

@@ -393,3 +393,84 @@ def test_upscale_linear_rows_and_bilateral_columns():
     assert out[0].tolist() == [4, 4, 20, 20]
     assert out[2].tolist() == [8, 8, 20, 20]
     assert out[1].tolist() == [6, 6, 20, 20]
+
+
+# ------------------------------------------------------ variants (Sec. III-E, V)
+
+def test_simple_fills_hand_example():
+    """Sec. III-E's two simple fills on one row: GCPs at x = 1 (D = 10) and
+    x = 6 (D = 20).  Mode 1 takes the GCP closer in distance (x = 3: i = 2,
+    j = 3 -> left; x = 4: i = 3, j = 2 -> right; no tie here); mode 2 the
+    smaller disparity; both copy a lone side and give 0 to a GCP-free row."""
+    med = np.array([[0, 10, 0, 0, 0, 0, 20, 0], [0] * 8], np.int16)
+    gcp = np.array([[0, 1, 0, 0, 0, 0, 1, 0], [0] * 8], np.uint8)
+    hl = np.zeros((2, 8), np.uint8)
+    assert oracle.fill(med, gcp, hl, 3, mode=1).tolist() == [
+        [10, 10, 10, 10, 20, 20, 20, 20], [0] * 8]
+    assert oracle.fill(med, gcp, hl, 3, mode=2).tolist() == [
+        [10, 10, 10, 10, 10, 10, 20, 20], [0] * 8]
+    # equal distance goes to the right-hand GCP
+    med2 = np.array([[5, 0, 9]], np.int16)
+    gcp2 = np.array([[1, 0, 1]], np.uint8)
+    assert oracle.fill(med2, gcp2, np.zeros((1, 3), np.uint8), 3, mode=1).tolist() == [[5, 9, 9]]
+
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_simple_fills_match_brute(mode):
+    rng = np.random.default_rng(30 + mode)
+    med = rng.integers(0, 20, size=(6, 17)).astype(np.int16)
+    gcp = (rng.random((6, 17)) < 0.3).astype(np.uint8)
+    hl = rng_img(rng, 6, 17)
+    exp = brute.fill(med.tolist(), gcp.tolist(), hl.tolist(), 3, mode)
+    assert np.array_equal(oracle.fill(med, gcp, hl, 3, mode), as_np(exp, np.int16))
+
+
+@pytest.mark.parametrize("W,H,dmax,seed,kw", [
+    (14, 10, 6, 41, dict(arm_x_r=1)),
+    (13, 9, 4, 42, dict(arm_x_r=6, arm_x=2)),
+    (12, 8, 7, 43, dict(full_res=True)),
+    (11, 9, 5, 44, dict(full_res=True, arm_x_r=2, fill_mode=1)),
+    (12, 10, 6, 45, dict(fill_mode=2)),
+])
+def test_variants_whole_path_match_brute(W, H, dmax, seed, kw):
+    p = make_pair(W, H, dmax, segments=3, seed=seed)
+    q = oracle.Params(arm_x=kw.get("arm_x", 4), arm_y=3, arm_x_r=kw.get("arm_x_r", -1),
+                      fill_mode=kw.get("fill_mode", 0), full_res=kw.get("full_res", False))
+    got = oracle.disparity(p.left, p.right, dmax, q)
+    exp = brute.disparity(p.left.tolist(), p.right.tolist(), dmax, q.lambda_ad, q.lambda_mc,
+                          q.cost_scale, q.color_delta, q.arm_x, q.arm_y, q.fill_T,
+                          ax_r=q.cap_r(), fill_mode=q.fill_mode, full_res=q.full_res)
+    for k, dt in (("half_l", np.uint8), ("arms_l", np.uint8), ("arms_r", np.uint8),
+                  ("disp_l", np.int16), ("disp_r", np.int16), ("min_l", np.uint32),
+                  ("min_r", np.uint32), ("gcp", np.uint8), ("median", np.int16),
+                  ("filled", np.int16), ("out", np.int16)):
+        assert np.array_equal(got[k], as_np(exp[k], dt)), k
+    if q.full_res:
+        assert got["out"].shape == (H, W) and np.array_equal(got["out"], got["filled"])
+        assert np.array_equal(got["half_l"], oracle.gray(p.left))
+
+
+def test_separate_right_arm_cap_only_changes_right_arms():
+    p = make_pair(60, 30, 16, segments=4, seed=46)
+    a = oracle.disparity(p.left, p.right, 16, oracle.Params())
+    b = oracle.disparity(p.left, p.right, 16, oracle.Params(arm_x_r=7))
+    assert np.array_equal(a["arms_l"], b["arms_l"])
+    assert np.array_equal(a["disp_l"], b["disp_l"])
+    assert b["arms_r"][..., :2].max() <= 7
+    assert np.array_equal(b["arms_r"][..., 2:], a["arms_r"][..., 2:])
+    # the right image's arms are those of its own cap
+    ref = oracle.arms(oracle.downscale(oracle.gray(p.right)), oracle.Params(arm_x=7))
+    assert np.array_equal(b["arms_r"], ref)
+
+
+def test_full_resolution_constant_shift_returns_the_shift():
+    """At full resolution a shift s of a noise texture is found as s itself
+    (no halving) wherever the cross region and census stay clear of the
+    borders and of the uncovered columns."""
+    s, W, H = 5, 120, 30
+    left, right = textured_shift_pair(W, H, s, seed=47)
+    q = oracle.Params(full_res=True)
+    r = oracle.disparity(left, right, 16, q)
+    assert r["min_l"][2:-2, s + 2 + q.arm_x:-2 - q.arm_x].max() == 0
+    inner = r["disp_l"][2:-2, s + 2 + q.arm_x:-2 - q.arm_x]
+    assert np.mean(inner == s) > 0.95
