@@ -51,10 +51,18 @@ extern "C" {
 /* params.flags */
 #define STEREO_F_KEEP_INTERMEDIATES 1u /* keep per-call planes for stereo_get_intermediate */
 #define STEREO_F_STAGE_TIMING 2u       /* time each stage with HIP events on the stream     */
+#define STEREO_F_FULL_RES 4u           /* no 2x downscale / upscale: the method on the
+                                          original images over d in [0, Dmax-1] (Sec. V);
+                                          W <= STEREO_MAX_SIDE / 2                            */
 
 /* Parameters of the method.  Defaults (stereo_default_params) are the paper's:
  * lambda_AD = 0.3, lambda_MC = 2.3 and T = 3 (Sec. V); arm caps 21 (x) and
- * 31 (y) and colour threshold 13 (Table II footnote, Sec. V). */
+ * 31 (y) and colour threshold 13 (Table II footnote, Sec. V); the bilateral
+ * fill; one horizontal cap for both images.  The paper's variants: a
+ * separate horizontal cap for the right image (arm_x_r, Sec. V), the two
+ * simpler non-GCP fills (fill_mode, Sec. III-E) and the full-resolution
+ * mode with caps 41 and 61 (STEREO_F_FULL_RES, Sec. V; it needs a smaller
+ * cost_scale, e.g. 512, to meet the aggregate bound below). */
 typedef struct stereo_params {
   uint32_t size;       /* must equal sizeof(stereo_params)                          */
   float lambda_ad;     /* Eq. 4, on brightness normalised to [0,1]; > 0              */
@@ -65,6 +73,9 @@ typedef struct stereo_params {
   int32_t arm_y;       /* per-side cap of the vertical arms M, N; 0..127             */
   int32_t fill_T;      /* T of Sec. III-E (bilateral filling and upscale); >= 0      */
   uint32_t flags;      /* STEREO_F_*                                                 */
+  int32_t arm_x_r;     /* horizontal cap of the right image; -1 = arm_x; 0..127      */
+  int32_t fill_mode;   /* non-GCPs: 0 bilateral (Eq. 11), 1 the GCP closer in
+                          distance (right on equal distance), 2 the smaller disparity */
 } stereo_params;
 
 typedef struct stereo_ctx stereo_ctx; /* opaque, owned by the library */
@@ -90,8 +101,10 @@ const char* stereo_last_error(const stereo_ctx* ctx);
  *   W, H        : 2..STEREO_MAX_SIDE.
  *   Dmax        : 1..min(W, STEREO_MAX_DMAX).
  *   params      : NULL for the defaults; else size must match and values be
- *                 in range, including (2 arm_x + 1)(2 arm_y + 1) * C_max < 2^24
- *                 where C_max is the largest table cost.
+ *                 in range, including (2 max(arm_x, arm_x_r) + 1)(2 arm_y + 1)
+ *                 * C_max < 2^(32 - b), where C_max is the largest table cost
+ *                 and b the bits of D - 1 (D the searched range, at least 1
+ *                 bit): the winner-take-all keys pack the aggregate and d.
  *   out_disp    : device, int16 [H][W].
  * Scratch for each (W, H, Dmax, params) is allocated on first use and cached. */
 int stereo_disparity(stereo_ctx* ctx, const uint8_t* left, const uint8_t* right, int W, int H,

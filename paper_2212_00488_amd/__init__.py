@@ -5,5 +5,6 @@
 Importing the package loads nothing; the library is loaded on first use.
 """
 
-from .binding import (F_KEEP_INTERMEDIATES, F_STAGE_TIMING, STAGES, Params,  # noqa: F401
+from .binding import (F_FULL_RES, F_KEEP_INTERMEDIATES, F_STAGE_TIMING, STAGES,  # noqa: F401
+                      Params,
                       Stereo, StereoError, default_params, lib)

@@ -18,6 +18,7 @@ from .build import LIB
 OK, EINVAL, ENOMEM, EHIP, EUNIMPL = 0, -1, -2, -3, -4
 F_KEEP_INTERMEDIATES = 1
 F_STAGE_TIMING = 2
+F_FULL_RES = 4
 STAGES = ("downscale", "census_arms", "cost_aggregate_wta", "chunk_min",
           "crosscheck_median_fill", "upscale")
 
@@ -41,7 +42,8 @@ class Params(ctypes.Structure):
                 ("lambda_mc", ctypes.c_float), ("cost_scale", ctypes.c_int32),
                 ("color_delta", ctypes.c_int32), ("arm_x", ctypes.c_int32),
                 ("arm_y", ctypes.c_int32), ("fill_T", ctypes.c_int32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("arm_x_r", ctypes.c_int32),
+                ("fill_mode", ctypes.c_int32)]
 
 
 class SoftParams(ctypes.Structure):
@@ -210,7 +212,7 @@ class Stereo:
                                     ctypes.byref(params) if params is not None else None,
                                     out.data_ptr(), _stream_handle(stream))
         self._raise(rc)
-        self._last_shape = (W, H, dmax)
+        self._last_shape = (W, H, dmax, params is not None and bool(params.flags & F_FULL_RES))
         return out
 
     def disparity_batch(self, lefts, rights, dmax: int, params: Params | None = None,
@@ -231,7 +233,7 @@ class Stereo:
             n, W, H, int(dmax), ctypes.byref(params) if params is not None else None,
             arr(*[t.data_ptr() for t in outs]), _stream_handle(stream))
         self._raise(rc)
-        self._last_shape = (W, H, dmax)
+        self._last_shape = (W, H, dmax, params is not None and bool(params.flags & F_FULL_RES))
         return outs
 
     def stage_times(self, reset: bool = True):
@@ -243,7 +245,8 @@ class Stereo:
 
     def intermediate(self, name: str, d: int = 0, stream=None) -> np.ndarray:
         """A plane of the last call made with F_KEEP_INTERMEDIATES, as numpy."""
-        W, H, dmax = self._last_shape
+        W, H, dmax, full = self._last_shape
+        X, Y = (W, H) if full else ((W + 1) // 2, (H + 1) // 2)
         if name == "lut":
             buf = np.zeros(263, np.uint16)
             rc = lib().stereo_get_intermediate(self._h, I_LUT, 0, buf.ctypes.data, buf.nbytes,
@@ -251,7 +254,7 @@ class Stereo:
             self._raise(rc)
             return buf
         which, dt, tail = INTERMEDIATES[name]
-        buf = np.zeros(((H + 1) // 2, (W + 1) // 2) + tail, dt)
+        buf = np.zeros((Y, X) + tail, dt)
         rc = lib().stereo_get_intermediate(self._h, which, int(d), buf.ctypes.data, buf.nbytes,
                                            _stream_handle(stream))
         self._raise(rc)

@@ -8,6 +8,7 @@
 //   k_wta      combine the d-chunk minima                       (Eq. 9)
 //   k_refine   cross-check, 3x3 median and bilateral filling    (Eq. 10, Sec. III-E, Eq. 11)
 //   k_upscale  bilateral x / linear y upscale to full res      (Step8)
+//   k_gray_full, k_copy_out: the full-resolution mode's ends   (Sec. V)
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -124,7 +125,8 @@ __device__ __forceinline__ void grow_arms(const uint8_t* p, int c, int delta, in
 //           and at the image border; packed m | n<<8 | M<<16 | N<<24
 // grid: (ceil(X/64), ceil(Y/32), 2 * npair), block (64, 16).
 __global__ void __launch_bounds__(1024) k_feat(const uint8_t* __restrict__ half, int X, int Y,
-                                               int delta, int arm_x, int arm_y, int XP, int pad,
+                                               int delta, int arm_x_l, int arm_x_r, int arm_y,
+                                               int XP, int pad,
                                                int XA, uint32_t* __restrict__ pk,
                                                uint32_t* __restrict__ arms) {
   constexpr int TXW = 64 + 2 * (kMaxArm + 2);
@@ -132,6 +134,8 @@ __global__ void __launch_bounds__(1024) k_feat(const uint8_t* __restrict__ half,
   __shared__ uint8_t ty[kFeatRows + 2 * kMaxArm][64];
   const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kFeatRows, img = blockIdx.z;
   const uint8_t* h = half + (size_t)img * X * Y;
+  // horizontal cap of this image (the two images may differ, Sec. V)
+  const int arm_x = (img & 1) ? arm_x_r : arm_x_l;
   const int hx = arm_x + 2, wx = 64 + 2 * hx;
   for (int r = threadIdx.y; r < kFeatRows + 2; r += 16) {
     const uint8_t* src = h + (size_t)clampi(y0 - 1 + r, 0, Y - 1) * X;
@@ -214,7 +218,8 @@ struct MatchArgs {
   const uint32_t* arms;   // [2*npair][Y][XA]  zero past column X
   const uint16_t* tab;    // [7][kTabPitch]
   uint32_t* keys;         // [npair][nchunk][2][nk]  (min CA) << 8 | argmin d
-  int X, Y, XP, pad, XA, nk, arm_x, arm_y;
+  int X, Y, XP, pad, XA, nk, arm_x, arm_x_r, arm_y;
+  int dbits;              // key = CA << dbits | d
   int nbands, nchunk, dlo, dhi;
   int nstrips, ngroups;   // groups = strips x bands x 2 bases x pairs
   uint32_t pk_bytes, arms_bytes;  // sizes of the pk and arms buffers
@@ -271,7 +276,8 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   const int nb = yb - ya, o0 = y0 - ya, o1 = y1 - ya;
   const int span = a.dhi - a.dlo;
   const int d0 = a.dlo + (chunk * span) / a.nchunk, d1 = a.dlo + ((chunk + 1) * span) / a.nchunk;
-  const int hx = (a.arm_x + 2) & ~1;   // row buffer starts at column x0 - hx (even)
+  // row buffer starts at column x0 - hx (even); hx covers this base's arms
+  const int hx = ((base ? a.arm_x_r : a.arm_x) + 2) & ~1;
   const int sgn = base ? 1 : -1;       // other-image column is x + sgn * d
   const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(a.pk, a.pk_bytes);
   const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(a.arms, a.arms_bytes);
@@ -433,7 +439,7 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
         // immediate offset of the LDS read
         const int lo = fin_base - (M + 1) * 64, hi = fin_base + N * 64;
         const uint32_t ca = s_plane[hi + k * kWaves * 64] - s_plane[lo + k * kWaves * 64];
-        const uint32_t kv = (ca << 8) | (uint32_t)d;
+        const uint32_t kv = (ca << a.dbits) | (uint32_t)d;
         key[k] = kv < key[k] ? kv : key[k];
       }
     }
@@ -450,23 +456,23 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
       if (k * kWaves < nout) {
         out[(size_t)(ya + r) * X + x] = key[k];
         // a debug run covers the single disparity dlo, so the key holds CA
-        if (DBG && dbg) a.dbg_ca[(size_t)(ya + r) * X + x] = key[k] >> 8;
+        if (DBG && dbg) a.dbg_ca[(size_t)(ya + r) * X + x] = key[k] >> a.dbits;
       }
     }
   }
 }
 
 // ----------------------------------------------------------------- k_wta
-// Minimum key over the d-chunks for both bases: D = key & 255 (Eq. 9; the
-// key order makes the smallest d win ties), and the minimum aggregate
-// key >> 8 when mincost != NULL.  Four pixels per thread; planes have the
+// Minimum key over the d-chunks for both bases: D = key & (2^dbits - 1)
+// (Eq. 9; the key order makes the smallest d win ties), and the minimum
+// aggregate key >> dbits when mincost != NULL.  Four pixels per thread; planes have the
 // padded stride nk (a multiple of 64 pixels).
 // grid: (ceil(nk / 1024), npair), block 256.
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef int16_t i16x4 __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_wta(const uint32_t* __restrict__ keys, int nchunk,
-                                             int nk, int16_t* __restrict__ disp,
+                                             int nk, int dbits, int16_t* __restrict__ disp,
                                              uint32_t* __restrict__ mincost) {
   const int i = (blockIdx.x * 256 + threadIdx.x) * 4;
   const int pair = blockIdx.y;
@@ -480,10 +486,12 @@ __global__ void __launch_bounds__(256) k_wta(const uint32_t* __restrict__ keys, 
       m.x = min(m.x, v.x); m.y = min(m.y, v.y); m.z = min(m.z, v.z); m.w = min(m.w, v.w);
     }
     const size_t o = (size_t)(2 * pair + b) * nk + i;
+    const uint32_t dm = (1u << dbits) - 1u;
     *reinterpret_cast<i16x4*>(disp + o) =
-        i16x4{(int16_t)(m.x & 255u), (int16_t)(m.y & 255u), (int16_t)(m.z & 255u),
-              (int16_t)(m.w & 255u)};
-    if (mincost) *reinterpret_cast<u32x4*>(mincost + o) = u32x4{m.x >> 8, m.y >> 8, m.z >> 8, m.w >> 8};
+        i16x4{(int16_t)(m.x & dm), (int16_t)(m.y & dm), (int16_t)(m.z & dm), (int16_t)(m.w & dm)};
+    if (mincost)
+      *reinterpret_cast<u32x4*>(mincost + o) =
+          u32x4{m.x >> dbits, m.y >> dbits, m.z >> dbits, m.w >> dbits};
   }
 }
 
@@ -493,7 +501,9 @@ __global__ void __launch_bounds__(256) k_wta(const uint32_t* __restrict__ keys, 
 // a non-GCP takes the nearest GCPs left (x-i) and right (x+j): linear
 // interpolation from M(x-i) toward M(x+j), rounded half up, when they differ
 // by at most T, else the side of strictly closer brightness (the right one on
-// a tie) (Sec. III-E).  One side only: copy it; none: 0.
+// a tie) (Sec. III-E).  One side only: copy it; none: 0.  fill_mode 1 and 2
+// are the two simpler fills Sec. III-E describes first: the GCP closer in
+// distance (the right one at equal distance), or the smaller disparity.
 // grid: (Y, npair), block 256.
 __device__ __forceinline__ int floor_div_pos(int n, int d) {  // d > 0
   return n >= 0 ? n / d : -((-n + d - 1) / d);
@@ -512,7 +522,7 @@ __device__ __forceinline__ int median9(int* v) {
 
 __global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp, int nk,
                                                 const uint32_t* __restrict__ pk, int XP, int pad,
-                                                int X, int Y, int T,
+                                                int X, int Y, int T, int fill_mode,
                                                 uint8_t* __restrict__ gcp_out,
                                                 int16_t* __restrict__ med_out,
                                                 int16_t* __restrict__ filled) {
@@ -575,7 +585,11 @@ __global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp
       const int xl = s_xl[x], xr = next;
       if (xl >= 0 && xr < X) {
         const int i = x - xl, j = xr - x, dla = s_med[xl], drb = s_med[xr];
-        if (iabs(dla - drb) <= T) {
+        if (fill_mode == 1) {
+          v = i < j ? dla : drb;
+        } else if (fill_mode == 2) {
+          v = min(dla, drb);
+        } else if (iabs(dla - drb) <= T) {
           v = dla + floor_div_pos(2 * i * (drb - dla) + (i + j), 2 * (i + j));
         } else {
           const int ch = s_h[x];
@@ -591,6 +605,27 @@ __global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp
     }
     fo[x] = (int16_t)v;
   }
+}
+
+// ------------------------------------------------------------ k_gray_full
+// Full-resolution mode (the method on the original images, Sec. V): the
+// "half" image is the gray image itself.  grid: (ceil(W/256), H, 2 npair),
+// block 256.
+__global__ void __launch_bounds__(256) k_gray_full(PairPtrs pp, int W, int H,
+                                                   uint8_t* __restrict__ half) {
+  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, img = blockIdx.z;
+  if (x >= W) return;
+  const uint8_t* rgb = (img & 1) ? pp.right[img >> 1] : pp.left[img >> 1];
+  half[(size_t)img * W * H + (size_t)y * W + x] = (uint8_t)gray_of(rgb + ((size_t)y * W + x) * 3);
+}
+
+// Full-resolution mode: the filled map is the output (no upscale).
+// grid: (ceil(W*H/256), npair), block 256.
+__global__ void __launch_bounds__(256) k_copy_out(PairPtrs pp, const int16_t* __restrict__ filled,
+                                                  int n) {
+  const int i = blockIdx.x * 256 + threadIdx.x, pair = blockIdx.y;
+  if (i >= n) return;
+  pp.out[pair][i] = filled[(size_t)pair * n + i];
 }
 
 // ------------------------------------------------------------- k_upscale

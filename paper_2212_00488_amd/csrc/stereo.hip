@@ -33,14 +33,25 @@ void build_tables(const stereo_params& p, uint16_t ad[256], uint16_t mc[7]) {
 bool same_params(const stereo_params& a, const stereo_params& b) {
   return a.lambda_ad == b.lambda_ad && a.lambda_mc == b.lambda_mc && a.cost_scale == b.cost_scale &&
          a.color_delta == b.color_delta && a.arm_x == b.arm_x && a.arm_y == b.arm_y &&
-         a.fill_T == b.fill_T;
+         a.fill_T == b.fill_T && a.arm_x_r == b.arm_x_r && a.fill_mode == b.fill_mode &&
+         (a.flags & STEREO_F_FULL_RES) == (b.flags & STEREO_F_FULL_RES);
+}
+
+bool full_res(const stereo_params& p) { return (p.flags & STEREO_F_FULL_RES) != 0; }
+
+// Bits of the disparity field of the winner-take-all keys: enough for D - 1.
+int key_dbits(int D) {
+  int b = 1;
+  while ((1 << b) < D) ++b;
+  return b;
 }
 
 }  // namespace stereo_host
 
 namespace stereo_host {
 
-int check_params(stereo_ctx* c, const stereo_params& p) {
+// Checks p for a search range of D disparities (D >= 1); resolves arm_x_r.
+int check_params(stereo_ctx* c, stereo_params& p, int D) {
   if (p.size != sizeof(stereo_params))
     return fail(c, STEREO_EINVAL, "params.size %u != %zu", p.size, sizeof(stereo_params));
   if (!(p.lambda_ad > 0.f) || !std::isfinite(p.lambda_ad) || !(p.lambda_mc > 0.f) ||
@@ -50,15 +61,21 @@ int check_params(stereo_ctx* c, const stereo_params& p) {
     return fail(c, STEREO_EINVAL, "cost_scale %d outside 1..1024", p.cost_scale);
   if (p.color_delta < 0 || p.color_delta > 256)
     return fail(c, STEREO_EINVAL, "color_delta %d outside 0..256", p.color_delta);
-  if (p.arm_x < 0 || p.arm_x > 127 || p.arm_y < 0 || p.arm_y > 127)
-    return fail(c, STEREO_EINVAL, "arm caps must be in 0..127");
+  if (p.arm_x_r == -1) p.arm_x_r = p.arm_x;
+  if (p.arm_x < 0 || p.arm_x > 127 || p.arm_y < 0 || p.arm_y > 127 || p.arm_x_r < 0 ||
+      p.arm_x_r > 127)
+    return fail(c, STEREO_EINVAL, "arm caps must be in 0..127 (arm_x_r: -1 or 0..127)");
+  if (p.fill_mode < 0 || p.fill_mode > 2) return fail(c, STEREO_EINVAL, "fill_mode %d outside 0..2", p.fill_mode);
   if (p.fill_T < 0 || p.fill_T > 1023) return fail(c, STEREO_EINVAL, "fill_T outside 0..1023");
   uint16_t ad[256], mc[7];
   build_tables(p, ad, mc);
   const double cmax = (double)ad[255] + mc[6];
-  const double bound = (2.0 * p.arm_x + 1) * (2.0 * p.arm_y + 1) * cmax;
-  if (bound >= 16777216.0)
-    return fail(c, STEREO_EINVAL, "(2 arm_x + 1)(2 arm_y + 1) C_max = %.0f must be < 2^24", bound);
+  const int ax = std::max(p.arm_x, p.arm_x_r), dbits = key_dbits(D);
+  const double bound = (2.0 * ax + 1) * (2.0 * p.arm_y + 1) * cmax;
+  if (bound >= std::ldexp(1.0, 32 - dbits))
+    return fail(c, STEREO_EINVAL,
+                "(2 arm_x + 1)(2 arm_y + 1) C_max = %.0f must be < 2^%d for D = %d "
+                "(lower cost_scale or the arm caps)", bound, 32 - dbits, D);
   return 0;
 }
 
@@ -74,7 +91,7 @@ void free_plan(Plan* pl) {
 // registers within bounds; d-chunks raise the workgroup count to fill the CUs.
 void plan_geometry(Plan& pl, int num_cu) {
   // the row buffer spans x0 - hx .. x0 + 63 + arm_x, hx = arm_x + 1 rounded up to even
-  pl.ns = (66 + 2 * pl.p.arm_x + 127) / 128;
+  pl.ns = (66 + 2 * std::max(pl.p.arm_x, pl.p.arm_x_r) + 127) / 128;
   const int pr = plane_rows(pl.ns);
   // Output rows of a band are spread over the 16 waves, KMAX per thread
   // (template steps 8..36).  The finalize of a band reads plane rows up to
@@ -113,7 +130,12 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
               Plan** out) {
   Plan* pl = new Plan();
   pl->W = W; pl->H = H; pl->Dmax = Dmax; pl->npair = npair;
-  pl->X = (W + 1) / 2; pl->Y = (H + 1) / 2; pl->D = (Dmax + 1) / 2;
+  if (full_res(p)) {
+    pl->X = W; pl->Y = H; pl->D = Dmax;
+  } else {
+    pl->X = (W + 1) / 2; pl->Y = (H + 1) / 2; pl->D = (Dmax + 1) / 2;
+  }
+  pl->dbits = key_dbits(pl->D);
   pl->p = p;
   build_tables(p, pl->lut_ad, pl->lut_mc);
   pl->cmax = pl->lut_ad[255] + pl->lut_mc[6];
@@ -210,7 +232,7 @@ MatchArgs match_args(const Plan& pl, int dlo, int dhi, int nchunk) {
   MatchArgs a{};
   a.pk = pl.pk; a.arms = pl.arms; a.tab = pl.tab; a.keys = pl.keys;
   a.X = pl.X; a.Y = pl.Y; a.XP = pl.XP; a.pad = pl.pad; a.XA = pl.XA; a.nk = pl.nk;
-  a.arm_x = pl.p.arm_x; a.arm_y = pl.p.arm_y;
+  a.arm_x = pl.p.arm_x; a.arm_x_r = pl.p.arm_x_r; a.arm_y = pl.p.arm_y; a.dbits = pl.dbits;
   a.pk_bytes = (uint32_t)((size_t)2 * pl.npair * pl.Y * pl.XP * 4);
   a.arms_bytes = (uint32_t)((size_t)2 * pl.npair * pl.Y * pl.XA * 4);
   a.nbands = pl.nbands; a.nchunk = nchunk; a.dlo = dlo; a.dhi = dhi;
@@ -263,26 +285,35 @@ int run(stereo_ctx* c, Plan& pl, const PairPtrs& pp, int npair, bool keep, bool 
   }
   auto mark = [&](int i) { if (ev) (void)hipEventRecord(ev[i], s); };
   dim3 b2(64, 4);
+  const bool full = full_res(pl.p);
   mark(0);
-  hipLaunchKernelGGL(k_prep, dim3((X + 63) / 64, (Y + kPrepRows - 1) / kPrepRows, 2 * npair), b2,
-                     0, s, pp, pl.W, pl.H, X, Y, pl.half);
+  if (full)
+    hipLaunchKernelGGL(k_gray_full, dim3((X + 255) / 256, Y, 2 * npair), dim3(256), 0, s, pp, X, Y,
+                       pl.half);
+  else
+    hipLaunchKernelGGL(k_prep, dim3((X + 63) / 64, (Y + kPrepRows - 1) / kPrepRows, 2 * npair),
+                       b2, 0, s, pp, pl.W, pl.H, X, Y, pl.half);
   mark(1);
   hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + kFeatRows - 1) / kFeatRows, 2 * npair),
                      dim3(64, 16), 0,
-                     s, pl.half, X, Y, pl.p.color_delta, pl.p.arm_x, pl.p.arm_y, pl.XP, pl.pad,
-                     pl.XA, pl.pk, pl.arms);
+                     s, pl.half, X, Y, pl.p.color_delta, pl.p.arm_x, pl.p.arm_x_r, pl.p.arm_y,
+                     pl.XP, pl.pad, pl.XA, pl.pk, pl.arms);
   mark(2);
   launch_match(pl, match_args(pl, 0, pl.D, pl.nchunk), npair, s);
   mark(3);
   hipLaunchKernelGGL(k_wta, dim3((pl.nk + 1023) / 1024, npair), dim3(256), 0, s, pl.keys,
-                     pl.nchunk, pl.nk, pl.disp, keep ? pl.mincost : nullptr);
+                     pl.nchunk, pl.nk, pl.dbits, pl.disp, keep ? pl.mincost : nullptr);
   mark(4);
   hipLaunchKernelGGL(k_refine, dim3(Y, npair), dim3(256), 0, s, pl.disp, pl.nk, pl.pk, pl.XP,
-                     pl.pad, X, Y, pl.p.fill_T, keep ? pl.gcp : nullptr, keep ? pl.med : nullptr,
-                     pl.filled);
+                     pl.pad, X, Y, pl.p.fill_T, pl.p.fill_mode, keep ? pl.gcp : nullptr,
+                     keep ? pl.med : nullptr, pl.filled);
   mark(5);
-  hipLaunchKernelGGL(k_upscale, dim3((X + 63) / 64, (Y + 3) / 4, npair), b2, 0, s, pp, pl.filled,
-                     pl.W, pl.H, X, Y, pl.p.fill_T);
+  if (full)
+    hipLaunchKernelGGL(k_copy_out, dim3((X * Y + 255) / 256, npair), dim3(256), 0, s, pp,
+                       pl.filled, X * Y);
+  else
+    hipLaunchKernelGGL(k_upscale, dim3((X + 63) / 64, (Y + 3) / 4, npair), b2, 0, s, pp,
+                       pl.filled, pl.W, pl.H, X, Y, pl.p.fill_T);
   mark(6);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(c, STEREO_EHIP, "kernel launch: %s", hipGetErrorString(e));
@@ -303,7 +334,10 @@ int common_checks(stereo_ctx* c, int W, int H, int Dmax, const stereo_params* pa
   } else {
     stereo_default_params(p);
   }
-  return check_params(c, *p);
+  const bool full = (p->flags & STEREO_F_FULL_RES) != 0;
+  if (full && W > STEREO_MAX_SIDE / 2)
+    return fail(c, STEREO_EINVAL, "full-resolution mode needs W <= %d", STEREO_MAX_SIDE / 2);
+  return check_params(c, *p, full ? Dmax : (Dmax + 1) / 2);
 }
 
 }  // namespace stereo_host
@@ -324,6 +358,8 @@ void stereo_default_params(stereo_params* p) {
   p->arm_y = 31;
   p->fill_T = 3;
   p->flags = 0;
+  p->arm_x_r = -1;
+  p->fill_mode = 0;
 }
 
 int stereo_create(stereo_ctx** out, int device, size_t mem_cap) {

@@ -37,10 +37,25 @@ def test_default_params_are_the_papers():
     if not os.path.exists(LIB):
         pytest.skip("library not built")
     p = sm.default_params()
-    assert p.size == ctypes.sizeof(sm.Params) == 36
+    assert p.size == ctypes.sizeof(sm.Params) == 44
     assert abs(p.lambda_ad - 0.3) < 1e-6 and abs(p.lambda_mc - 2.3) < 1e-6
-    assert (p.cost_scale, p.color_delta, p.arm_x, p.arm_y, p.fill_T, p.flags) == (
-        1024, 13, 21, 31, 3, 0)
+    assert (p.cost_scale, p.color_delta, p.arm_x, p.arm_y, p.fill_T, p.flags, p.arm_x_r,
+            p.fill_mode) == (1024, 13, 21, 31, 3, 0, -1, 0)
+
+
+def test_struct_layouts_match_header():
+    """The ctypes mirrors list the header's struct members in order."""
+    from paper_2212_00488_amd import binding as b
+    text = open(HEADER).read()
+    for cname, cls in (("stereo_params", b.Params), ("stereo_soft_params", b.SoftParams),
+                       ("stereo_server_config", b.ServerConfig),
+                       ("stereo_server_result", b.ServerResult)):
+        body = re.search(r"typedef struct " + cname + r" \{(.*?)\} " + cname + ";", text, re.S)
+        assert body, cname
+        members = re.findall(r"^\s*[A-Za-z_0-9]+\s+([A-Za-z_0-9]+(?:\s*,\s*[A-Za-z_0-9]+)*);",
+                             body.group(1), re.M)
+        names = [n.strip() for m in members for n in m.split(",")]
+        assert names == [f[0] for f in cls._fields_], (cname, names)
 
 
 def test_intermediate_ids_match_header():

@@ -51,7 +51,8 @@ def oracle_params(p):
     return oracle.Params(lambda_ad=float(np.float32(p.lambda_ad)),
                          lambda_mc=float(np.float32(p.lambda_mc)), cost_scale=p.cost_scale,
                          color_delta=p.color_delta, arm_x=p.arm_x, arm_y=p.arm_y,
-                         fill_T=p.fill_T)
+                         fill_T=p.fill_T, arm_x_r=p.arm_x_r, fill_mode=p.fill_mode,
+                         full_res=bool(p.flags & 4))
 
 
 def run_gpu(ctx, left, right, dmax, params):
@@ -233,3 +234,45 @@ def test_memory_cap(sm):
         c.disparity(lt, rt, 32)
     assert e.value.code == -2
     c.close()
+
+
+# ------------------------------------------------ variants (Sec. III-E, Sec. V)
+
+@pytest.mark.parametrize("kw", [
+    dict(fill_mode=1), dict(fill_mode=2), dict(arm_x_r=7), dict(arm_x=9, arm_x_r=40),
+    dict(arm_x_r=0, fill_mode=1),
+])
+def test_variants_bit_exact(sm, ctx, kw):
+    pair = make_pair(150, 90, 30, segments=4, seed=11)
+    full_parity(sm, ctx, pair.left, pair.right, 30, keep_params(sm, **kw), label=str(kw))
+
+
+@pytest.mark.parametrize("W,H,dmax,kw", [
+    (160, 120, 32, dict(arm_x=41, arm_y=61)),            # the paper's full-size caps
+    (97, 53, 20, dict(arm_x=41, arm_y=61, fill_mode=2)),
+    (640, 480, 64, dict(arm_x=41, arm_y=61)),
+    (301, 77, 145, dict(arm_x=41, arm_y=61, cost_scale=512, arm_x_r=30)),  # 8-bit d field
+])
+def test_full_resolution_mode_bit_exact(sm, ctx, W, H, dmax, kw):
+    pair = make_pair(W, H, dmax, segments=5, seed=12)
+    p = sm.default_params(flags=sm.F_KEEP_INTERMEDIATES | sm.F_FULL_RES, **kw)
+    full_parity(sm, ctx, pair.left, pair.right, dmax, p, label=f"full {W}x{H} {kw}")
+
+
+def test_variant_parameter_checks(sm, ctx):
+    pair = make_pair(64, 48, 16, segments=3, seed=13)
+    lt = torch.from_numpy(pair.left).cuda()
+    rt = torch.from_numpy(pair.right).cuda()
+    for kw in (dict(fill_mode=3), dict(arm_x_r=-2), dict(arm_x_r=128),
+               # 83 x 123 x 1936 exceeds 2^24 with an 8-bit d field
+               dict(flags=sm.F_FULL_RES, arm_x=41, arm_y=61)):
+        with pytest.raises(sm.StereoError) as e:
+            dmax = 145 if "flags" in kw else 16
+            big = torch.zeros((64, 160, 3), dtype=torch.uint8, device="cuda")
+            if "flags" in kw:
+                ctx.disparity(big, big, dmax, sm.default_params(**kw))
+            else:
+                ctx.disparity(lt, rt, 16, sm.default_params(**kw))
+        assert e.value.code == -1, kw
+    # still usable
+    ctx.disparity(lt, rt, 16)
