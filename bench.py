@@ -29,11 +29,20 @@ W, H, DMAX = 1436, 992, 145
 PAPER_FPS = 40.0  # Table II / abstract, GTX 780 Ti, Adirondack at this size
 # Peak integer VALU rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
-# Algorithmic integer operations per half-res evaluation (x, y, d), both
-# base images: the cost (abs-diff, xor, popcount, table add: 4, shared by the
-# two bases through Eq. 6) and, per base, row prefix add, CA_x difference,
-# column prefix add, CA difference and the WTA compare (5 x 2).
-OPS_PER_EVAL = 4 + 2 * 5
+# Work model of the fused cost / aggregation / WTA kernel per half-res
+# evaluation e = (x, y, d), both bases, with O(1) window sums:
+#   integer VALU ops ~ 40: per base, the cost of the pixel pair (difference,
+#   xor, popcount, table index: 4) evaluated on the strip and its arm halo,
+#   the row-prefix scan step and add, the two window ends and difference of
+#   CA_x, the column-prefix add, the two window ends and difference of CA,
+#   and the packed-key compare (about 20 per base);
+#   LDS bytes 48: per base, the row-prefix store 4, the two CA_x window-end
+#   loads 8, the column-prefix store 4 and the two CA window-end loads 8.
+OPS_PER_EVAL = 40
+LDS_BYTES_PER_EVAL = 48
+# LDS bandwidth figure used beside it: 128 B per clock per CU (the CDNA3
+# rate; a lower bound for gfx950) x 256 CUs x 2.4 GHz.
+PEAK_LDS_BYTES = 128 * 256 * 2.4e9
 
 
 def parse():
@@ -290,7 +299,11 @@ def main():
                      "peak": round(PEAK_INT_OPS / 1e12, 3), "unit": "Tops/s",
                      "frac": round(achieved / PEAK_INT_OPS, 4), "traffic": measured_traffic(),
                      "ops_per_eval": OPS_PER_EVAL, "evals_per_launch": evals,
-                     "avg_launch_ms": round(stage_ms["cost_aggregate_wta"], 5)},
+                     "avg_launch_ms": round(stage_ms["cost_aggregate_wta"], 5),
+                     "lds": {"bytes_per_eval": LDS_BYTES_PER_EVAL,
+                             "achieved_TBps": round(LDS_BYTES_PER_EVAL * evals / t_match / 1e12, 3),
+                             "peak_TBps": round(PEAK_LDS_BYTES / 1e12, 2),
+                             "frac": round(LDS_BYTES_PER_EVAL * evals / t_match / PEAK_LDS_BYTES, 4)}},
     }
     ctx.close()
     if args.serve_requests > 0:

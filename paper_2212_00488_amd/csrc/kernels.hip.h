@@ -26,6 +26,7 @@ constexpr int kThreads = kWaves * 64;
 constexpr int kKMax = 34;         // most output rows per k_match thread (band <= 544 rows)
 constexpr int kLdsBytes = 163840; // LDS per workgroup on gfx950
 constexpr int kXcds = 8;          // accelerator complex dies, each with its own L2
+constexpr int kRowBatch = 2;      // k_match rows whose lookups and scans interleave
 
 
 __device__ __forceinline__ int iabs(int v) { return v < 0 ? -v : v; }
@@ -328,8 +329,8 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
 
   for (int d = d0; d < d1; ++d) {
     const uint32_t vo = vb + (uint32_t)(sgn * d * 4);
-    // ---- row pass over this wave's rows r0..r1-1, two rows at a time (their
-    // lookups and scans interleave), the loads of the next two rows in flight.
+    // ---- row pass over this wave's rows r0..r1-1, kRowBatch rows at a time
+    // (their lookups and scans interleave), the loads of the next batch in flight.
     // CA_x of a row is added to a running column sum, so the plane receives
     // the column prefix within the wave's segment of rows.
     struct RowIn { u32x2 b[NS], o[NS]; uint32_t am; };
@@ -370,47 +371,42 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
       return cax;
     };
     uint32_t run = 0;
-    // the partner of row r is r + 1, or r itself (loaded, never stored) at
-    // the end of an odd segment
-    auto partner = [&](int r) { return r + 1 < r1 ? r + 1 : r; };
-    auto process_pair = [&](int r, const RowIn& A, const RowIn& B) {
-      uint32_t ca0[NS], ca1[NS], cb0[NS], cb1[NS], pa[NS], pb[NS];
+    // Rows go in batches of kRowBatch: their lookups and scans interleave.  A
+    // batch running past the segment end loads its last row again in place
+    // of the missing ones and never stores them.
+    auto row_of = [&](int r, int i) { return r + i < r1 ? r + i : r1 - 1; };
+    auto load_batch = [&](int r, RowIn (&in)[kRowBatch]) {
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        ca0[s] = cost(A.b[s].x, A.o[s].x);
-        ca1[s] = cost(A.b[s].y, A.o[s].y);
-        cb0[s] = cost(B.b[s].x, B.o[s].x);
-        cb1[s] = cost(B.b[s].y, B.o[s].y);
-      }
+      for (int i = 0; i < kRowBatch; ++i) load_row(row_of(r, i), in[i]);
+    };
+    auto process_batch = [&](int r, const RowIn (&in)[kRowBatch]) {
+      uint32_t c0[kRowBatch][NS], c1[kRowBatch][NS], pr[kRowBatch][NS];
 #pragma unroll
-      for (int s = 0; s < NS; ++s) {
-        pa[s] = wave_scan_incl(ca0[s] + ca1[s]);
-        pb[s] = wave_scan_incl(cb0[s] + cb1[s]);
-      }
-      run += finish_row(r, ca0, ca1, pa, A.am);
-      s_plane[(r + 1) * 64 + lane] = run;
-      if (r + 1 < r1) {
-        run += finish_row(r + 1, cb0, cb1, pb, B.am);
-        s_plane[(r + 2) * 64 + lane] = run;
+      for (int i = 0; i < kRowBatch; ++i)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          c0[i][s] = cost(in[i].b[s].x, in[i].o[s].x);
+          c1[i][s] = cost(in[i].b[s].y, in[i].o[s].y);
+        }
+#pragma unroll
+      for (int i = 0; i < kRowBatch; ++i)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) pr[i][s] = wave_scan_incl(c0[i][s] + c1[i][s]);
+#pragma unroll
+      for (int i = 0; i < kRowBatch; ++i) {
+        if (i > 0 && r + i >= r1) break;
+        run += finish_row(r + i, c0[i], c1[i], pr[i], in[i].am);
+        s_plane[(r + i + 1) * 64 + lane] = run;
       }
     };
-    RowIn a0, b0, a1, b1;  // two buffer sets, used in turn
-    if (r0 < r1) {
-      load_row(r0, a0);
-      load_row(partner(r0), b0);
-    }
-    for (int r = r0; r < r1; r += 4) {
-      if (r + 2 < r1) {
-        load_row(r + 2, a1);
-        load_row(partner(r + 2), b1);
-      }
-      process_pair(r, a0, b0);
-      if (r + 2 >= r1) break;
-      if (r + 4 < r1) {
-        load_row(r + 4, a0);
-        load_row(partner(r + 4), b0);
-      }
-      process_pair(r + 2, a1, b1);
+    RowIn in0[kRowBatch], in1[kRowBatch];  // two buffer sets, used in turn
+    if (r0 < r1) load_batch(r0, in0);
+    for (int r = r0; r < r1; r += 2 * kRowBatch) {
+      if (r + kRowBatch < r1) load_batch(r + kRowBatch, in1);
+      process_batch(r, in0);
+      if (r + kRowBatch >= r1) break;
+      if (r + 2 * kRowBatch < r1) load_batch(r + 2 * kRowBatch, in0);
+      process_batch(r + kRowBatch, in1);
     }
     s_seg[wave][c] = run;
     __syncthreads();

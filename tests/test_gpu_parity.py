@@ -212,10 +212,16 @@ def test_errors_leave_context_usable(sm, ctx):
     bad.size = 12
     with pytest.raises(sm.StereoError):
         ctx.disparity(lt, rt, 16, bad)
-    for kw in (dict(arm_x=128), dict(lambda_ad=0.0), dict(cost_scale=2048),
-               dict(arm_x=127, arm_y=127)):
+    for kw in (dict(arm_x=128), dict(lambda_ad=0.0), dict(cost_scale=2048)):
         with pytest.raises(sm.StereoError):
             ctx.disparity(lt, rt, 16, sm.default_params(**kw))
+    # 201 x 255 x 1936 > 2^24, the aggregate field of the keys for D = 145
+    # (8 bits of d); with D = 8 (3 bits) the same caps are valid
+    wide = torch.zeros((32, 300, 3), dtype=torch.uint8, device="cuda")
+    with pytest.raises(sm.StereoError) as e:
+        ctx.disparity(wide, wide, 290, sm.default_params(arm_x=100, arm_y=127))
+    assert "2^24" in ctx.last_error()
+    ctx.disparity(wide, wide, 16, sm.default_params(arm_x=100, arm_y=127))
     L = sm.lib()
     assert L.stereo_disparity(ctx._h, None, rt.data_ptr(), 64, 32, 16, None,
                               lt.data_ptr(), None) == -1

@@ -128,25 +128,37 @@ def test_arm_and_temperature_variants_match_oracle(ctx):
 
 
 def test_lambda_gradient_matches_gpu_central_differences(ctx):
-    """Central differences of the GPU loss itself (float32, so a relative
-    step of 1e-2 and a tolerance of 2e-3)."""
+    """Central differences of the GPU forward itself for both lambdas, a
+    coarse check of the adjoint on the kernels alone (the 1e-3 checks above
+    compare against the FP64 reference gradient, itself pinned by float64
+    central differences).  The differenced function is a fixed random linear
+    functional of d_hat (the L1 loss has kinks a finite step crosses), summed
+    in float64 on the host; its gradient comes from the adjoint with g_dhat =
+    the weights.  The float32 forward with fixed-point costs carries about
+    1e-5 of noise per d_hat, about 4e-4 in the functional, so a step of 1e-2
+    lambda leaves about 1% of noise and truncation: tolerance 1.5e-2."""
     L, R, G, M = float_pairs(2, 64, 48, 32, 540, noise=0.002)
     p = osoft.SoftParams()
-    _, _, _, _, glam = run_gpu(ctx, L, R, G, M, 32, p)
+    w = np.random.default_rng(541).standard_normal((2, 24, 32)).astype(np.float32)
+    left, right = to_dev(L), to_dev(R)
+    lam = torch.tensor([p.lambda_ad, p.lambda_census], dtype=torch.float32, device=DEV,
+                       requires_grad=True)
+    d = soft_disparity(ctx, left, right, lam, 32, sp_from(p))
+    (d * to_dev(w)).sum().backward()
+    glam = lam.grad.cpu().numpy()
     base = np.array([p.lambda_ad, p.lambda_census])
+
+    def f(lv):
+        with torch.no_grad():
+            lt = torch.tensor(lv, dtype=torch.float32, device=DEV)
+            dh = soft_disparity(ctx, left, right, lt, 32, sp_from(p)).cpu().numpy()
+        return float(np.sum(dh.astype(np.float64) * w))
+
     for k in range(2):
-        h = 1e-2 * base[k]
-        vals = []
-        for sgn in (1, -1):
-            lam = base.copy()
-            lam[k] += sgn * h
-            with torch.no_grad():
-                lt = torch.tensor(lam, dtype=torch.float32, device=DEV)
-                d = soft_disparity(ctx, to_dev(L), to_dev(R), lt, 32, sp_from(p))
-                vals.append(float(l1_loss(ctx, d, to_dev(G.astype(np.int16)),
-                                          to_dev(M.astype(np.uint8))).cpu()[0]))
-        fd = (vals[0] - vals[1]) / (2 * h)
-        assert abs(fd - glam[k]) <= 2e-3 * abs(glam[k]) + 1e-7, (k, fd, glam[k])
+        e = np.zeros(2)
+        e[k] = 1e-2 * base[k]
+        fd = (f(base + e) - f(base - e)) / (2 * e[k])
+        assert abs(fd - glam[k]) <= 1.5e-2 * abs(glam[k]) + 1e-6, (k, fd, glam[k])
 
 
 def test_backward_is_deterministic_and_batch_matches_single(ctx):
