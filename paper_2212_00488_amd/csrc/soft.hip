@@ -375,7 +375,7 @@ int stereo_soft_backward(stereo_ctx* c, const float* left, const float* right, i
   }
   hipLaunchKernelGGL(k_soft_gfull, dim3((W + 255) / 256, H, 2 * pl->n), dim3(256), 0, stream,
                      pl->g_half, W, H, X, Y, g_left, g_right);
-  hipLaunchKernelGGL(k_soft_lam, dim3(1), dim3(256), 0, stream, pl->lam_part, (int)lam_off,
+  hipLaunchKernelGGL(k_soft_lam, dim3(1), dim3(1024), 0, stream, pl->lam_part, (int)lam_off,
                      g_lambdas);
   return launch_status(c);
 }

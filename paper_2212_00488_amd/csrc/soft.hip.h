@@ -43,6 +43,7 @@ namespace stereo_dev {
 namespace {
 
 constexpr int kSoftBR = 32;  // output rows per k_soft_tr workgroup
+constexpr int kTrBatch = 8;  // source rows per batch of loads in k_soft_tr
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
@@ -111,6 +112,7 @@ __global__ void __launch_bounds__(256) k_soft_size(const uint32_t* __restrict__ 
   const uint32_t c = a[(size_t)y * XA + x];
   const int M = (c >> 16) & 255, N = c >> 24;
   int s = 0;
+#pragma unroll 8
   for (int r = y - M; r <= y + N; ++r) {
     const uint32_t v = a[(size_t)r * XA + x];
     s += (int)(v & 255u) + (int)((v >> 8) & 255u) + 1;
@@ -384,10 +386,13 @@ struct TrArgs {
 
 __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
   constexpr int BR = kSoftBR;
-  __shared__ float s_d1[4][BR][64];
+  // s_d1 (phase 1, per wave [BR][64]) and s_d2 (phase 2, [BR][65]) share
+  // one buffer: phase 2 starts after the barrier that ends the use of s_d1
+  __shared__ float s_buf[4 * BR * 64];
   __shared__ float s_g[BR][128];
-  __shared__ float s_d2[BR][65];
   __shared__ float2 s_red[4];
+  auto s_d1 = reinterpret_cast<float(*)[BR][64]>(s_buf);
+  auto s_d2 = reinterpret_cast<float(*)[65]>(s_buf);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int strip = blockIdx.x % a.nstrips, band = blockIdx.x / a.nstrips;
   const int dj = blockIdx.y, d = a.dlo + dj, pair = blockIdx.z;
@@ -398,8 +403,9 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
   const uint32_t* arm = a.arms + (size_t)(2 * pair) * Y * a.XA;
 
   for (int r = 0; r < BR; ++r) s_d1[wave][r][lane] = 0.f;
-  for (int i = t; i < BR * 65; i += 256) (&s_d2[0][0])[i] = 0.f;
-  // phase 1: column difference arrays
+  // phase 1: column difference arrays.  The loads of kTrBatch source rows
+  // are issued together (and the next batch's before this one's updates),
+  // so the chain of LDS updates does not wait on global memory row by row.
   {
     const int cg = wave & 1, rh = wave >> 1;
     const int col = x0 - 32 + 64 * cg + lane;
@@ -407,18 +413,36 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
     const int ys0 = max(0, y0 - a.arm_y), ys1 = min(Y, y0 + BR + a.arm_y);
     const int mid = (ys0 + ys1) >> 1;
     const int ya = rh ? mid : ys0, yb = rh ? ys1 : mid;
-    for (int y = ya; y < yb; ++y) {
-      float gv = 0.f;
-      uint32_t am = 0u;
-      if (cv) {
-        gv = g[(size_t)y * X + col];
-        am = arm[(size_t)y * a.XA + col];
+    float gv[2][kTrBatch];
+    uint32_t am[2][kTrBatch];
+    auto fetch = [&](int y, int buf) {
+#pragma unroll
+      for (int i = 0; i < kTrBatch; ++i) {
+        const int yy = min(y + i, yb - 1);
+        gv[buf][i] = cv ? g[(size_t)yy * X + col] : 0.f;
+        am[buf][i] = cv ? arm[(size_t)yy * a.XA + col] : 0u;
       }
-      const int lo = y - (int)((am >> 16) & 255u) - y0, hi = y + (int)(am >> 24) + 1 - y0;
-      if (gv != 0.f && hi > 0 && lo < BR) {
-        s_d1[wave][max(lo, 0)][lane] += gv;
-        if (hi < BR) s_d1[wave][hi][lane] -= gv;
+    };
+    auto scatter = [&](int y, int buf) {
+#pragma unroll
+      for (int i = 0; i < kTrBatch; ++i) {
+        const int yy = y + i;
+        const float v = gv[buf][i];
+        const uint32_t m = am[buf][i];
+        const int lo = yy - (int)((m >> 16) & 255u) - y0, hi = yy + (int)(m >> 24) + 1 - y0;
+        if (yy < yb && v != 0.f && hi > 0 && lo < BR) {
+          s_d1[wave][max(lo, 0)][lane] += v;
+          if (hi < BR) s_d1[wave][hi][lane] -= v;
+        }
       }
+    };
+    if (ya < yb) fetch(ya, 0);
+    for (int y = ya; y < yb; y += 2 * kTrBatch) {
+      if (y + kTrBatch < yb) fetch(y + kTrBatch, 1);
+      scatter(y, 0);
+      if (y + kTrBatch >= yb) break;
+      if (y + 2 * kTrBatch < yb) fetch(y + 2 * kTrBatch, 0);
+      scatter(y + kTrBatch, 1);
     }
   }
   __syncthreads();
@@ -430,7 +454,8 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
     }
   }
   __syncthreads();
-  // phase 2: row difference arrays, prefix, cost derivatives
+  // phase 2: row difference arrays, prefix, cost derivatives.  Each wave owns
+  // the rows r = wave + 4 i; their arm and pixel loads are issued first.
   const float lam_ad = a.lam[0], lam_c = a.lam[1];
   const float k2 = 255.f * 1.4426950408889634f / lam_ad;
   const float kt = 255.f / lam_ad, ka = 1.f / (lam_ad * lam_ad), kc = 1.f / (lam_c * lam_c);
@@ -439,36 +464,62 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
   const uint2* spl = a.sp + (size_t)(2 * pair) * Y * a.XS + a.pads;
   const uint2* spr = a.sp + (size_t)(2 * pair + 1) * Y * a.XS + a.pads;
   float* tout = a.t + ((size_t)dj * a.npair + pair) * plane;
-  for (int r = wave; r < BR; r += 4) {
-    const int y = y0 + r;
-    if (y >= Y) break;
+  constexpr int RPW = BR / 4;  // rows per wave
+  uint32_t am2[RPW][2];
+  uint2 pl_[RPW], pr_[RPW];
+  const int x = x0 + lane;
+  const bool xin = x < X, dv = x - d >= 0;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int y = min(y0 + wave + 4 * i, Y - 1);
 #pragma unroll
     for (int cg = 0; cg < 2; ++cg) {
       const int col = x0 - 32 + 64 * cg + lane;
-      if (col >= 0 && col < X) {
-        const float gx = s_g[r][64 * cg + lane];
-        const uint32_t am = arm[(size_t)y * a.XA + col];
-        const int lo = col - (int)(am & 255u) - x0, hi = col + (int)((am >> 8) & 255u) + 1 - x0;
-        if (gx != 0.f && hi > 0 && lo < 64) {
-          atomicAdd(&s_d2[r][max(lo, 0)], gx);
-          if (hi < 64) atomicAdd(&s_d2[r][hi], -gx);
-        }
+      am2[i][cg] = (col >= 0 && col < X) ? arm[(size_t)y * a.XA + col] : 0u;
+    }
+    pl_[i] = xin ? spl[(size_t)y * a.XS + x] : make_uint2(0u, 0u);
+    pr_[i] = (xin && dv) ? spr[(size_t)y * a.XS + x - d] : make_uint2(0u, 0u);
+  }
+  // this wave's rows of s_d2 start at zero (only this wave touches them)
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int r = wave + 4 * i;
+    s_d2[r][lane] = 0.f;
+    if (lane == 0) s_d2[r][64] = 0.f;
+  }
+  WAVE_LDS_ORDER();
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int r = wave + 4 * i;
+    if (y0 + r >= Y) break;
+#pragma unroll
+    for (int cg = 0; cg < 2; ++cg) {
+      const int col = x0 - 32 + 64 * cg + lane;
+      const float gx = s_g[r][64 * cg + lane];
+      const uint32_t m = am2[i][cg];
+      const int lo = col - (int)(m & 255u) - x0, hi = col + (int)((m >> 8) & 255u) + 1 - x0;
+      if (col >= 0 && col < X && gx != 0.f && hi > 0 && lo < 64) {
+        atomicAdd(&s_d2[r][max(lo, 0)], gx);
+        if (hi < 64) atomicAdd(&s_d2[r][hi], -gx);
       }
     }
-    WAVE_LDS_ORDER();
+  }
+  WAVE_LDS_ORDER();
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    const int r = wave + 4 * i, y = y0 + r;
+    if (y >= Y) break;
     const float gc = wave_scan_incl_f(s_d2[r][lane]);
-    const int x = x0 + lane;
-    if (x < X) {
+    if (xin) {
       float tv = 0.f;
-      if (x - d >= 0) {
-        const uint2 L = spl[(size_t)y * a.XS + x], R = spr[(size_t)y * a.XS + x - d];
-        const float di = __uint_as_float(L.x) - __uint_as_float(R.x);
+      if (dv) {
+        const float di = __uint_as_float(pl_[i].x) - __uint_as_float(pr_[i].x);
         const float ad = fabsf(di);
         const float E = fast_exp2(-ad * k2);
         const float sg = di > 0.f ? 1.f : (di < 0.f ? -1.f : 0.f);
         tv = gc * kt * E * sg;
         pa += gc * (-E * 255.f * ad * ka);
-        const int hh = __builtin_popcount(L.y ^ R.y);
+        const int hh = __builtin_popcount(pl_[i].y ^ pr_[i].y);
         pcs += gc * (-fast_exp2(-(float)hh * l2c) * (float)hh * kc);
       }
       tout[(size_t)y * X + x] = tv;
@@ -545,20 +596,32 @@ __global__ void __launch_bounds__(256) k_soft_gfull(const float* __restrict__ g_
 }
 
 // ------------------------------------------------------------ k_soft_lam
-// Sum of the per-workgroup lambda partials in a fixed order.
-// grid: 1, block 256.
-__global__ void __launch_bounds__(256) k_soft_lam(const float2* __restrict__ part, int count,
-                                                  float* __restrict__ g_lam) {
-  __shared__ float2 s[256];
+// Sum of the per-workgroup lambda partials in a fixed order: thread t sums
+// entries t + 1024 j into four accumulators (j mod 4), then a tree.
+// grid: 1, block 1024.
+__global__ void __launch_bounds__(1024) k_soft_lam(const float2* __restrict__ part, int count,
+                                                   float* __restrict__ g_lam) {
+  __shared__ float2 s[1024];
   const int t = threadIdx.x;
-  float2 acc = make_float2(0.f, 0.f);
-  for (int i = t; i < count; i += 256) {
-    acc.x += part[i].x;
-    acc.y += part[i].y;
+  float2 acc[4] = {};
+  int i = t, j = 0;
+  for (; i + 3 * 1024 < count; i += 4 * 1024) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float2 v = part[i + u * 1024];
+      acc[u].x += v.x;
+      acc[u].y += v.y;
+    }
   }
-  s[t] = acc;
+  for (; i < count; i += 1024, ++j) {
+    const float2 v = part[i];
+    acc[j & 3].x += v.x;
+    acc[j & 3].y += v.y;
+  }
+  s[t] = make_float2((acc[0].x + acc[1].x) + (acc[2].x + acc[3].x),
+                     (acc[0].y + acc[1].y) + (acc[2].y + acc[3].y));
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = 512; o > 0; o >>= 1) {
     if (t < o) {
       s[t].x += s[t + o].x;
       s[t].y += s[t + o].y;
