@@ -17,7 +17,7 @@ using namespace stereo_dev;
 namespace stereo_host {
 
 constexpr int kSoftMaxPairs = 64;
-constexpr size_t kSlabBudget = size_t(256) << 20;  // gca + t planes of one automatic slab
+constexpr size_t kSlabBudget = size_t(512) << 20;  // dL/dCA (then t) + dL/dCA_x planes of a slab
 
 struct SoftPlan {
   int n = 0, W = 0, H = 0, Dmax = 0, X = 0, Y = 0, D = 0;
@@ -39,7 +39,8 @@ struct SoftPlan {
   float2* part = nullptr;      // [n][nchunk][Y][X]
   float4* pc = nullptr;        // [n][Y][X]
   float* gca = nullptr;        // [nds][n][Y][X]
-  float* tpl = nullptr;        // [nds][n][Y][X]
+  float* gcax = nullptr;       // [nds][n][Y][X] dL/dCA_x (the gca planes then hold t)
+  int ring = 64;               // rows of k_soft_tcol's difference-array ring
   float* g_half = nullptr;     // [2n][Y][X]
   float2* lam_part = nullptr;  // [lam_count]
   uint64_t last_use = 0;
@@ -137,6 +138,7 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
   pl->nds = p.slab > 0 ? std::min(p.slab, D)
                        : (int)std::max<size_t>(1, std::min<size_t>(D, kSlabBudget / (2 * n * npix * 4)));
   pl->nbands_tr = (Y + kSoftBR - 1) / kSoftBR;
+  while (pl->ring < 2 * p.arm_y + 2) pl->ring *= 2;
   const int nslab = (D + pl->nds - 1) / pl->nds;
   pl->lam_count = (size_t)nslab * pl->nds * n * pl->nstrips * pl->nbands_tr;
 
@@ -169,11 +171,14 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
   pl->part = carve<float2>(cur, (size_t)n * pl->nchunk * npix);
   pl->pc = carve<float4>(cur, n * npix);
   pl->gca = carve<float>(cur, (size_t)pl->nds * n * npix);
-  pl->tpl = carve<float>(cur, (size_t)pl->nds * n * npix);
+  pl->gcax = carve<float>(cur, (size_t)pl->nds * n * npix);
   pl->g_half = carve<float>(cur, nimg * npix);
   pl->lam_part = carve<float2>(cur, pl->lam_count);
   // zero padding of the arm and pixel planes (kernels write the image part)
-  e = hipMemset(pl->arms, 0, nimg * Y * pl->XA * 4);
+  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_soft_tcol),
+                          hipFuncAttributeMaxDynamicSharedMemorySize,
+                          4 * pl->ring * 64 * (int)sizeof(float));
+  if (e == hipSuccess) e = hipMemset(pl->arms, 0, nimg * Y * pl->XA * 4);
   if (e == hipSuccess) e = hipMemset(pl->sp, 0, nimg * Y * pl->XS * 8);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
@@ -361,17 +366,20 @@ int stereo_soft_backward(stereo_ctx* c, const float* left, const float* right, i
     const int dhi = std::min(pl->D, dlo + pl->nds), nds = dhi - dlo;
     const int nch = std::min(nds, fill_chunks(groups, c->num_cu, nds));
     launch_soft_agg<true>(*pl, soft_args(*pl, lambdas, dlo, dhi, nch), stream);
+    hipLaunchKernelGGL(k_soft_tcol, dim3((X + 63) / 64, (nds + 3) / 4, pl->n), dim3(64, 4),
+                       4 * pl->ring * 64 * sizeof(float), stream, pl->gca, pl->arms, X, Y, pl->XA,
+                       pl->p.arm_y, pl->ring, pl->n, nds, pl->gcax);
     TrArgs ta{};
-    ta.gca = pl->gca; ta.arms = pl->arms; ta.sp = pl->sp; ta.lam = lambdas; ta.t = pl->tpl;
+    ta.gcax = pl->gcax; ta.arms = pl->arms; ta.sp = pl->sp; ta.lam = lambdas; ta.t = pl->gca;
     ta.lam_part = pl->lam_part + lam_off;
     ta.X = X; ta.Y = Y; ta.XS = pl->XS; ta.pads = pl->pads; ta.XA = pl->XA;
-    ta.arm_y = pl->p.arm_y; ta.npair = pl->n; ta.dlo = dlo;
+    ta.npair = pl->n; ta.dlo = dlo;
     ta.nstrips = pl->nstrips; ta.nbands = pl->nbands_tr;
     dim3 tg((unsigned)(pl->nstrips * pl->nbands_tr), (unsigned)nds, (unsigned)pl->n);
     hipLaunchKernelGGL(k_soft_tr, tg, dim3(256), 0, stream, ta);
     lam_off += (size_t)tg.x * tg.y * tg.z;
     hipLaunchKernelGGL(k_soft_gimg, dim3((X + 255) / 256, Y, pl->n), dim3(256), 0, stream,
-                       pl->tpl, nds, dlo, pl->n, X, Y, pl->g_half);
+                       pl->gca, nds, dlo, pl->n, X, Y, pl->g_half);
   }
   hipLaunchKernelGGL(k_soft_gfull, dim3((W + 255) / 256, H, 2 * pl->n), dim3(256), 0, stream,
                      pl->g_half, W, H, X, Y, g_left, g_right);

@@ -18,9 +18,10 @@
 //   backward  k_soft_bprep  per-pixel constants of dL/dCA
 //             k_soft_agg    (GCA mode) recomputes CA for a slab of d and
 //                           writes dL/dCA planes
-//             k_soft_tr     transposed window sums (difference arrays +
-//                           prefix sums) back to dL/dC, then dC/d(dI),
-//                           dC/d(lambda) per pixel
+//             k_soft_tcol   transposed vertical window sums (difference
+//                           arrays in an LDS ring, one pass down each column)
+//             k_soft_tr     transposed horizontal window sums back to dL/dC,
+//                           then dC/d(dI), dC/d(lambda) per pixel
 //             k_soft_gimg   dL/d(half image) of both images over the slab
 //             k_soft_gfull  transposed downscale and gray: dL/d(RGB)
 //             k_soft_lam    fixed-order sum of the lambda partials
@@ -42,7 +43,7 @@ namespace stereo_dev {
 // carries its own copy (no relocatable device code).
 namespace {
 
-constexpr int kSoftBR = 32;  // output rows per k_soft_tr workgroup
+constexpr int kSoftBR = 16;  // output rows per k_soft_tr workgroup
 constexpr int kTrBatch = 8;  // source rows per batch of loads in k_soft_tr
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
@@ -354,108 +355,145 @@ __global__ void __launch_bounds__(256) k_soft_bprep(const float* __restrict__ in
   pc[o] = make_float4(is * zc, lse2[o], dhat[o], -g_dhat[o] * is * inv_tau);
 }
 
+// ------------------------------------------------------------ k_soft_tcol
+// Transpose of the vertical window sum (Eq. 8) for one disparity, one column
+// per lane, streaming down the column once:
+//   CA(x,y) = sum_{s=-M(x,y)}^{N(x,y)} CA_x(x,y+s)  gives
+//   dL/dCA_x(x,y') = sum of dL/dCA(x,y) over the y whose window holds y',
+// a difference array (+g at y - M, -g at y + N + 1) and a prefix down the
+// column.  A source row y only touches rows y - arm_y .. y + arm_y + 1, so
+// the array lives in an LDS ring of `ring` >= 2 arm_y + 2 rows per column:
+// after source y, row y - arm_y can receive nothing more, is added to the
+// running prefix, written out and its slot cleared.  Each lane owns its
+// column's ring, so the updates need no atomics.  Loads of kTrBatch rows
+// are issued together, the next batch's before this one's updates.
+// grid: (ceil(X/64), ceil(nds/4), n), block (64, 4) = one disparity per
+// wave; dynamic LDS 4 * ring * 64 floats.
+__global__ void __launch_bounds__(256) k_soft_tcol(const float* __restrict__ gca,
+                                                   const uint32_t* __restrict__ arms, int X,
+                                                   int Y, int XA, int arm_y, int ring, int npair,
+                                                   int nds, float* __restrict__ gcax) {
+  extern __shared__ float s_ring[];
+  const int lane = threadIdx.x, wave = threadIdx.y;
+  const int x = blockIdx.x * 64 + lane, dj = blockIdx.y * 4 + wave, pair = blockIdx.z;
+  if (dj >= nds) return;  // a whole wave; the kernel has no barrier
+  float* rg = s_ring + (size_t)wave * ring * 64 + lane;
+  for (int i = 0; i < ring; ++i) rg[i * 64] = 0.f;
+  const int mask = ring - 1;
+  const bool xv = x < X;
+  const size_t plane = (size_t)X * Y;
+  const float* g = gca + ((size_t)dj * npair + pair) * plane + x;
+  const uint32_t* am = arms + (size_t)(2 * pair) * Y * XA + x;
+  float* out = gcax + ((size_t)dj * npair + pair) * plane + x;
+  float carry = 0.f;
+  auto finalize = [&](int f) {
+    float* slot = rg + (f & mask) * 64;
+    carry += *slot;
+    *slot = 0.f;
+    if (xv) out[(size_t)f * X] = carry;
+  };
+  float gv[2][kTrBatch];
+  uint32_t av[2][kTrBatch];
+  auto fetch = [&](int y, int buf) {
+#pragma unroll
+    for (int i = 0; i < kTrBatch; ++i) {
+      const int yy = min(y + i, Y - 1);
+      gv[buf][i] = xv ? g[(size_t)yy * X] : 0.f;
+      av[buf][i] = xv ? am[(size_t)yy * XA] : 0u;
+    }
+  };
+  auto scatter = [&](int y, int buf) {
+#pragma unroll
+    for (int i = 0; i < kTrBatch; ++i) {
+      const int yy = y + i;
+      if (yy >= Y) break;
+      const float v = gv[buf][i];
+      const uint32_t m = av[buf][i];
+      if (v != 0.f) {
+        rg[((yy - (int)((m >> 16) & 255u)) & mask) * 64] += v;
+        const int e = yy + (int)(m >> 24) + 1;
+        if (e < Y) rg[(e & mask) * 64] -= v;
+      }
+      if (yy - arm_y >= 0) finalize(yy - arm_y);
+    }
+  };
+  fetch(0, 0);
+  for (int y = 0; y < Y; y += 2 * kTrBatch) {
+    if (y + kTrBatch < Y) fetch(y + kTrBatch, 1);
+    scatter(y, 0);
+    if (y + kTrBatch >= Y) break;
+    if (y + 2 * kTrBatch < Y) fetch(y + 2 * kTrBatch, 0);
+    scatter(y + kTrBatch, 1);
+  }
+  for (int f = max(0, Y - arm_y); f < Y; ++f) finalize(f);
+}
+
 // ------------------------------------------------------------- k_soft_tr
-// Transposed aggregation of one disparity over a 64-column strip and a band
-// of kSoftBR rows, then the cost derivatives there.
-//   CA(x,y) = sum_{s=-M(x,y)}^{N(x,y)} CA_x(x,y+s)  transposes to
-//   dL/dCA_x(x,y') = sum of dL/dCA(x,y) over the y whose window holds y':
-//   a difference array per column (+g at y - M, -g at y + N + 1), then a
-//   prefix down the column.  Likewise CA_x(x,y) = sum_{t=-m}^{n} C(x+t,y)
-//   transposes to a difference array along the row (+g at x - m, -g at
-//   x + n + 1) and a prefix along it, giving dL/dC.
+// Transpose of the horizontal window sum (Eq. 7) over a 64-column strip and
+// a band of kSoftBR rows for one disparity, then the cost derivatives there.
+//   CA_x(x,y) = sum_{t=-m}^{n} C(x+t,y) transposes to a difference array
+//   along the row (+g at x - m, -g at x + n + 1) and a prefix along it,
+//   giving dL/dC from dL/dCA_x (k_soft_tcol's planes).
 // Then with dI = L(x,y) - R(x-d,y), a = 255 |dI|, E = e^{-a/lambda_AD}:
 //   t = dL/dC * dC/d(dI) = dL/dC * (255 / lambda_AD) E sign(dI)
 //   dL/dlambda_AD     += dL/dC * (-E a / lambda_AD^2)
 //   dL/dlambda_census += dL/dC * (-e^{-H/lambda_census} H / lambda_census^2)
 // for x - d >= 0 (the constant cost of x - d < 0 has no derivative).
-// Phase 1: 4 waves = 2 column groups (columns x0 - 32 .. x0 + 95, which hold
-// every column whose horizontal window reaches the strip, arm_x <= 31) x 2
-// halves of the source rows; each lane owns one column of its wave's
-// difference array, so the updates need no atomics.  Phase 2: a wave per
-// band row; its 64 lanes scatter into the row's difference array with LDS
-// atomics (no other wave touches the row) and a DPP scan gives dL/dC.
+// The band's dL/dCA_x and arms over columns x0 - 32 .. x0 + 95 (every column
+// whose horizontal window reaches the strip, arm_x <= 31) are staged in LDS;
+// a lane per band row walks a quarter of those columns into its wave's
+// partial difference array, and a DPP scan over the summed partials gives
+// dL/dC.
+// grid: (strips * bands, nds, n), block 256.
 struct TrArgs {
-  const float* gca;         // [nds][n][Y][X]
+  const float* gcax;        // [nds][n][Y][X] dL/dCA_x
   const uint32_t* arms;     // [2n][Y][XA]
   const uint2* sp;          // [2n][Y][XS] padded pixel planes
   const float* lam;         // device [2]
   float* t;                 // [nds][n][Y][X]
   float2* lam_part;         // one {d/dlambda_AD, d/dlambda_census} per workgroup
-  int X, Y, XS, pads, XA, arm_y, npair, dlo, nstrips, nbands;
+  int X, Y, XS, pads, XA, npair, dlo, nstrips, nbands;
 };
 
 __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
   constexpr int BR = kSoftBR;
-  // s_d1 (phase 1, per wave [BR][64]) and s_d2 (phase 2, [BR][65]) share
-  // one buffer: phase 2 starts after the barrier that ends the use of s_d1
-  __shared__ float s_buf[4 * BR * 64];
-  __shared__ float s_g[BR][128];
+  // staged tiles (row pitch 129: a lane per row reads one column without
+  // bank conflicts) and four partial row difference arrays, one per wave
+  __shared__ float s_g[BR][129];
+  __shared__ uint16_t s_mn[BR][130];
+  __shared__ float s_d2[4][BR][65];
   __shared__ float2 s_red[4];
-  auto s_d1 = reinterpret_cast<float(*)[BR][64]>(s_buf);
-  auto s_d2 = reinterpret_cast<float(*)[65]>(s_buf);
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int strip = blockIdx.x % a.nstrips, band = blockIdx.x / a.nstrips;
   const int dj = blockIdx.y, d = a.dlo + dj, pair = blockIdx.z;
   const int X = a.X, Y = a.Y;
   const int x0 = strip * 64, y0 = band * BR;
   const size_t plane = (size_t)X * Y;
-  const float* g = a.gca + ((size_t)dj * a.npair + pair) * plane;
+  const float* g = a.gcax + ((size_t)dj * a.npair + pair) * plane;
   const uint32_t* arm = a.arms + (size_t)(2 * pair) * Y * a.XA;
-
-  for (int r = 0; r < BR; ++r) s_d1[wave][r][lane] = 0.f;
-  // phase 1: column difference arrays.  The loads of kTrBatch source rows
-  // are issued together (and the next batch's before this one's updates),
-  // so the chain of LDS updates does not wait on global memory row by row.
+  // stage dL/dCA_x and the horizontal arms (m | n << 8) of columns
+  // x0 - 32 .. x0 + 95: thread t takes column t & 127 of rows (t >> 7) + 2 k,
+  // all loads issued together
   {
-    const int cg = wave & 1, rh = wave >> 1;
-    const int col = x0 - 32 + 64 * cg + lane;
+    const int c = t & 127, col = x0 - 32 + c, r0 = t >> 7;
     const bool cv = col >= 0 && col < X;
-    const int ys0 = max(0, y0 - a.arm_y), ys1 = min(Y, y0 + BR + a.arm_y);
-    const int mid = (ys0 + ys1) >> 1;
-    const int ya = rh ? mid : ys0, yb = rh ? ys1 : mid;
-    float gv[2][kTrBatch];
-    uint32_t am[2][kTrBatch];
-    auto fetch = [&](int y, int buf) {
+    float v[BR / 2];
+    uint32_t m[BR / 2];
 #pragma unroll
-      for (int i = 0; i < kTrBatch; ++i) {
-        const int yy = min(y + i, yb - 1);
-        gv[buf][i] = cv ? g[(size_t)yy * X + col] : 0.f;
-        am[buf][i] = cv ? arm[(size_t)yy * a.XA + col] : 0u;
-      }
-    };
-    auto scatter = [&](int y, int buf) {
+    for (int k = 0; k < BR / 2; ++k) {
+      const int y = y0 + r0 + 2 * k;
+      const bool in = cv && y < Y;
+      v[k] = in ? g[(size_t)y * X + col] : 0.f;
+      m[k] = in ? arm[(size_t)y * a.XA + col] : 0u;
+    }
 #pragma unroll
-      for (int i = 0; i < kTrBatch; ++i) {
-        const int yy = y + i;
-        const float v = gv[buf][i];
-        const uint32_t m = am[buf][i];
-        const int lo = yy - (int)((m >> 16) & 255u) - y0, hi = yy + (int)(m >> 24) + 1 - y0;
-        if (yy < yb && v != 0.f && hi > 0 && lo < BR) {
-          s_d1[wave][max(lo, 0)][lane] += v;
-          if (hi < BR) s_d1[wave][hi][lane] -= v;
-        }
-      }
-    };
-    if (ya < yb) fetch(ya, 0);
-    for (int y = ya; y < yb; y += 2 * kTrBatch) {
-      if (y + kTrBatch < yb) fetch(y + kTrBatch, 1);
-      scatter(y, 0);
-      if (y + kTrBatch >= yb) break;
-      if (y + 2 * kTrBatch < yb) fetch(y + 2 * kTrBatch, 0);
-      scatter(y + kTrBatch, 1);
+    for (int k = 0; k < BR / 2; ++k) {
+      s_g[r0 + 2 * k][c] = v[k];
+      s_mn[r0 + 2 * k][c] = (uint16_t)(m[k] & 0xffffu);
     }
   }
-  __syncthreads();
-  if (wave < 2) {
-    float acc = 0.f;
-    for (int r = 0; r < BR; ++r) {
-      acc += s_d1[wave][r][lane] + s_d1[wave + 2][r][lane];
-      s_g[r][64 * wave + lane] = acc;
-    }
-  }
-  __syncthreads();
-  // phase 2: row difference arrays, prefix, cost derivatives.  Each wave owns
-  // the rows r = wave + 4 i; their arm and pixel loads are issued first.
+  for (int i = t; i < 4 * BR * 65; i += 256) (&s_d2[0][0][0])[i] = 0.f;
+  // operands of the cost derivative at the rows r = wave + 4 i of this wave
   const float lam_ad = a.lam[0], lam_c = a.lam[1];
   const float k2 = 255.f * 1.4426950408889634f / lam_ad;
   const float kt = 255.f / lam_ad, ka = 1.f / (lam_ad * lam_ad), kc = 1.f / (lam_c * lam_c);
@@ -465,51 +503,43 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
   const uint2* spr = a.sp + (size_t)(2 * pair + 1) * Y * a.XS + a.pads;
   float* tout = a.t + ((size_t)dj * a.npair + pair) * plane;
   constexpr int RPW = BR / 4;  // rows per wave
-  uint32_t am2[RPW][2];
   uint2 pl_[RPW], pr_[RPW];
   const int x = x0 + lane;
   const bool xin = x < X, dv = x - d >= 0;
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
     const int y = min(y0 + wave + 4 * i, Y - 1);
-#pragma unroll
-    for (int cg = 0; cg < 2; ++cg) {
-      const int col = x0 - 32 + 64 * cg + lane;
-      am2[i][cg] = (col >= 0 && col < X) ? arm[(size_t)y * a.XA + col] : 0u;
-    }
     pl_[i] = xin ? spl[(size_t)y * a.XS + x] : make_uint2(0u, 0u);
     pr_[i] = (xin && dv) ? spr[(size_t)y * a.XS + x - d] : make_uint2(0u, 0u);
   }
-  // this wave's rows of s_d2 start at zero (only this wave touches them)
-#pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int r = wave + 4 * i;
-    s_d2[r][lane] = 0.f;
-    if (lane == 0) s_d2[r][64] = 0.f;
-  }
-  WAVE_LDS_ORDER();
-#pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int r = wave + 4 * i;
-    if (y0 + r >= Y) break;
-#pragma unroll
-    for (int cg = 0; cg < 2; ++cg) {
-      const int col = x0 - 32 + 64 * cg + lane;
-      const float gx = s_g[r][64 * cg + lane];
-      const uint32_t m = am2[i][cg];
-      const int lo = col - (int)(m & 255u) - x0, hi = col + (int)((m >> 8) & 255u) + 1 - x0;
-      if (col >= 0 && col < X && gx != 0.f && hi > 0 && lo < 64) {
-        atomicAdd(&s_d2[r][max(lo, 0)], gx);
-        if (hi < 64) atomicAdd(&s_d2[r][hi], -gx);
+  __syncthreads();
+  // row difference arrays: lane r (< BR) of wave w walks the source columns
+  // 32 w .. 32 w + 31 of tile row r (+g at x - m, -g at x + n + 1, clipped to
+  // the strip), into the wave's own partial array: no atomics
+  if (lane < BR) {
+    const int r = lane;
+    float* dr = &s_d2[wave][r][0];
+#pragma unroll 4
+    for (int c = 32 * wave; c < 32 * wave + 32; ++c) {
+      const float gx = s_g[r][c];
+      const uint32_t mn = s_mn[r][c];
+      const int col = x0 - 32 + c;
+      const int lo = col - (int)(mn & 255u) - x0, hi = col + (int)(mn >> 8) + 1 - x0;
+      if (gx != 0.f && hi > 0 && lo < 64) {
+        dr[max(lo, 0)] += gx;
+        if (hi < 64) dr[hi] -= gx;
       }
     }
   }
-  WAVE_LDS_ORDER();
+  __syncthreads();
+  // prefix along each row (the four partials summed in a fixed order), then
+  // the cost derivatives
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
     const int r = wave + 4 * i, y = y0 + r;
     if (y >= Y) break;
-    const float gc = wave_scan_incl_f(s_d2[r][lane]);
+    const float dsum = (s_d2[0][r][lane] + s_d2[1][r][lane]) + (s_d2[2][r][lane] + s_d2[3][r][lane]);
+    const float gc = wave_scan_incl_f(dsum);
     if (xin) {
       float tv = 0.f;
       if (dv) {
