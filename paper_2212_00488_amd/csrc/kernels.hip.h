@@ -79,7 +79,7 @@ __global__ void __launch_bounds__(256) k_prep(PairPtrs pp, int W, int H, int X, 
 // brightness difference to any pixel exceeds 255, so that the cost table
 // returns C_max there (the x - d < 0 / x + d >= X convention) without a branch.
 constexpr uint32_t kSentinel = 1022u;
-constexpr int kFeatRows = 32;    // output rows per k_feat workgroup
+constexpr int kFeatRows = 16;    // output rows per k_feat workgroup (one pixel per thread)
 constexpr int kMaxArm = 127;
 
 // Grows the two arms of one axis for one pixel of value c: p points at the
@@ -117,15 +117,16 @@ __device__ __forceinline__ void grow_arms(const uint8_t* p, int c, int delta, in
   }
 }
 
-// One workgroup = 64 columns x 32 rows of one image, two pixels per thread.
-// Two LDS tiles of the half image (borders clamped): rows y0-1..y0+32 over
-// the columns reachable by the horizontal arms and the census, and rows
-// y0-arm_y..y0+31+arm_y over the 64 columns for the vertical arms.
+// One workgroup = 64 columns x kFeatRows rows of one image, one pixel per
+// thread.  Two LDS tiles of the half image (borders clamped): rows y0-1 ..
+// y0+kFeatRows over the columns reachable by the horizontal arms and the
+// census, and rows y0-arm_y .. y0+kFeatRows-1+arm_y over the 64 columns for
+// the vertical arms.
 //   census: 6 neighbours in three rows, bit k = [neighbour < centre]
 //   arms  : contiguous pixels with |I - I(centre)| < delta, capped per side
 //           and at the image border; packed m | n<<8 | M<<16 | N<<24
-// grid: (ceil(X/64), ceil(Y/32), 2 * npair), block (64, 16).
-__global__ void __launch_bounds__(1024) k_feat(const uint8_t* __restrict__ half, int X, int Y,
+// grid: (ceil(X/64), ceil(Y/kFeatRows), 2 * npair), block (64, kFeatRows).
+__global__ void __launch_bounds__(64 * kFeatRows) k_feat(const uint8_t* __restrict__ half, int X, int Y,
                                                int delta, int arm_x_l, int arm_x_r, int arm_y,
                                                int XP, int pad,
                                                int XA, uint32_t* __restrict__ pk,
@@ -138,20 +139,20 @@ __global__ void __launch_bounds__(1024) k_feat(const uint8_t* __restrict__ half,
   // horizontal cap of this image (the two images may differ, Sec. V)
   const int arm_x = (img & 1) ? arm_x_r : arm_x_l;
   const int hx = arm_x + 2, wx = 64 + 2 * hx;
-  for (int r = threadIdx.y; r < kFeatRows + 2; r += 16) {
+  for (int r = threadIdx.y; r < kFeatRows + 2; r += kFeatRows) {
     const uint8_t* src = h + (size_t)clampi(y0 - 1 + r, 0, Y - 1) * X;
     for (int c = threadIdx.x; c < wx; c += 64) tx[r][c] = src[clampi(x0 - hx + c, 0, X - 1)];
   }
   const int hy = kFeatRows + 2 * arm_y;
   const int cx = clampi(x0 + (int)threadIdx.x, 0, X - 1);
-  for (int r = threadIdx.y; r < hy; r += 16)
+  for (int r = threadIdx.y; r < hy; r += kFeatRows)
     ty[r][threadIdx.x] = h[(size_t)clampi(y0 - arm_y + r, 0, Y - 1) * X + cx];
   __syncthreads();
   const int lx = threadIdx.x, x = x0 + lx;
   if (x >= X) return;
-  for (int q = 0; q < kFeatRows / 16; ++q) {
-    const int ly = threadIdx.y + 16 * q, y = y0 + ly;
-    if (y >= Y) break;
+  {
+    const int ly = threadIdx.y, y = y0 + ly;
+    if (y >= Y) return;
     const uint8_t* row = &tx[ly + 1][hx + lx];   // row[i] = I(x + i, y)
     const int c = row[0];
     int bits = 0;
@@ -250,10 +251,16 @@ struct MatchArgs {
 template <int NS, int KMAX, bool DBG>
 __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   constexpr int PR = plane_rows(NS);
-  __shared__ uint16_t s_tab[kTab];
-  __shared__ uint32_t s_row[kWaves][NS * 128];
-  __shared__ uint32_t s_seg[kWaves][64];
-  __shared__ uint32_t s_plane[(PR + 1) * 64];  // row 0 = zeros (band row -1)
+  // One LDS block carved at constant offsets, the cost table first (LDS
+  // address 0), so table addresses fold into the read's offset field.
+  constexpr int kOffRow = ((kTab * 2 + 15) / 16) * 16;
+  constexpr int kOffSeg = kOffRow + kWaves * NS * 128 * 4;
+  constexpr int kOffPlane = kOffSeg + kWaves * 64 * 4;
+  __shared__ __align__(16) uint8_t s_lds[kOffPlane + (PR + 1) * 64 * 4];
+  uint16_t* s_tab = reinterpret_cast<uint16_t*>(s_lds);
+  auto s_row = reinterpret_cast<uint32_t(*)[NS * 128]>(s_lds + kOffRow);
+  auto s_seg = reinterpret_cast<uint32_t(*)[64]>(s_lds + kOffSeg);
+  uint32_t* s_plane = reinterpret_cast<uint32_t*>(s_lds + kOffPlane);  // row 0 = zeros
 
   const int t = threadIdx.x, lane = t & 63;
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);  // uniform: row offsets stay scalar
@@ -313,6 +320,10 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   }
   // plane word of (band row o0 + wave, column c); plane row = band row + 1
   const int fin_base = (o0 + wave + 1) * 64 + c;
+  // the key shift lives in a VGPR, so that shift-and-or with the scalar d
+  // is one instruction (one scalar operand per vector instruction)
+  uint32_t vdbits = (uint32_t)a.dbits;
+  __asm__ volatile("" : "+v"(vdbits));
   // byte offset of this lane's first column pair inside a padded pk row
   const uint32_t vb = (uint32_t)(a.pad + x0 - hx + 2 * lane) * 4u;
   __syncthreads();
@@ -321,8 +332,11 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   // cost of one pixel pair: byte offset of entry (h, 512 + diff) is
   // h * 2 * kTabPitch + 2 * diff + 1024, and the stored grays are doubled
   auto cost = [&](uint32_t b, uint32_t o) -> uint32_t {
-    const int e = (int)__builtin_popcount((b ^ o) >> 16) * (2 * kTabPitch) +
-                  ((int)(b & 0xffffu) - (int)(o & 0xffffu));
+    uint32_t hx;  // (b >> 16) ^ (o >> 16) in one instruction
+    __asm__("v_xor_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 "
+            "src1_sel:WORD_1" : "=v"(hx) : "v"(b), "v"(o));
+    const uint32_t h = __builtin_popcount(hx);
+    const int e = (int)h * (2 * kTabPitch) + ((int)(b & 0xffffu) - (int)(o & 0xffffu));
     return *reinterpret_cast<const uint16_t*>(tb + e);
   };
   const uint32_t vx = (uint32_t)x * 4u;
@@ -435,7 +449,7 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
         // immediate offset of the LDS read
         const int lo = fin_base - (M + 1) * 64, hi = fin_base + N * 64;
         const uint32_t ca = s_plane[hi + k * kWaves * 64] - s_plane[lo + k * kWaves * 64];
-        const uint32_t kv = (ca << a.dbits) | (uint32_t)d;
+        const uint32_t kv = (ca << vdbits) | (uint32_t)d;
         key[k] = kv < key[k] ? kv : key[k];
       }
     }

@@ -221,7 +221,7 @@ void soft_features(const SoftPlan& pl, const float* left, const float* right, hi
   hipLaunchKernelGGL(k_soft_prep, dim3((X + 63) / 64, (Y + 3) / 4, n2), dim3(64, 4), 0, s, left,
                      right, pl.W, pl.H, X, Y, pl.half_f, pl.half_u8);
   hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + kFeatRows - 1) / kFeatRows, n2),
-                     dim3(64, 16), 0, s, pl.half_u8, X, Y, pl.p.color_delta, pl.p.arm_x,
+                     dim3(64, kFeatRows), 0, s, pl.half_u8, X, Y, pl.p.color_delta, pl.p.arm_x,
                      pl.p.arm_x, pl.p.arm_y, X, 0, pl.XA, pl.pk, pl.arms);
   hipLaunchKernelGGL(k_soft_pack, dim3((X + 255) / 256, Y, n2), dim3(256), 0, s, pl.half_f, pl.pk,
                      X, Y, pl.XS, pl.pads, pl.sp);

@@ -295,7 +295,7 @@ int run(stereo_ctx* c, Plan& pl, const PairPtrs& pp, int npair, bool keep, bool 
                        b2, 0, s, pp, pl.W, pl.H, X, Y, pl.half);
   mark(1);
   hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + kFeatRows - 1) / kFeatRows, 2 * npair),
-                     dim3(64, 16), 0,
+                     dim3(64, kFeatRows), 0,
                      s, pl.half, X, Y, pl.p.color_delta, pl.p.arm_x, pl.p.arm_x_r, pl.p.arm_y,
                      pl.XP, pl.pad, pl.XA, pl.pk, pl.arms);
   mark(2);
