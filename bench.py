@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the served stream (0 skips it)")
+    ap.add_argument("--batch-steps", type=int, default=20,
+                    help="timed steps of the 8 x 1920x1080 batch (0 skips it)")
     ap.add_argument("--soft-steps", type=int, default=10,
                     help="timed steps of the differentiable head (0 skips it)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -120,6 +122,66 @@ def cpu_baseline(pair, seconds):
             "kind": "oracle",
             "sample": f"{frames} full {W}x{H} Dmax={DMAX} frames in {el:.1f} s",
             "mde_per_s": round(W * H * DMAX * fps / 1e6, 2)}
+
+
+def batch_leg(sm, steps):
+    """8 synthetic 1920x1080 pairs, Dmax = 256 (seeds 300-307), one batched
+    call per step: eager launches, the same call replayed from a captured HIP
+    graph, and the graph again after stereo_autotune picked the d-chunk count
+    of the fused kernel.  Pairs per second for each."""
+    import torch
+    from paper_2212_00488_amd.synth import workload_pairs
+
+    pairs = workload_pairs("batch8_1920x1080_d256")
+    dev = torch.device("cuda:0")
+    lefts = [torch.from_numpy(p.left).to(dev) for p in pairs]
+    rights = [torch.from_numpy(p.right).to(dev) for p in pairs]
+    outs = [torch.empty((1080, 1920), dtype=torch.int16, device=dev) for _ in pairs]
+    ctx = sm.Stereo(0)
+    stream = torch.cuda.Stream()
+
+    def call():
+        ctx.disparity_batch(lefts, rights, 256, outs=outs)
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        with torch.cuda.stream(stream):
+            fn()
+            torch.cuda.synchronize()
+            a.record(stream)
+            for _ in range(steps):
+                fn()
+            b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / steps
+
+    def graphed():
+        with torch.cuda.stream(stream):
+            call()  # the plan of this stream exists before the capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=stream):
+            call()
+        return g
+
+    res = {"workload": "8 x 1920x1080 RGB, Dmax=256 (960x540, D=128)"}
+    ms_eager = timed(call)
+    g = graphed()
+    ms_graph = timed(g.replay)
+    res["fixed"] = {"eager_pairs_per_s": round(8000.0 / ms_eager, 1),
+                    "graph_pairs_per_s": round(8000.0 / ms_graph, 1),
+                    "graph_ms_per_batch": round(ms_graph, 4)}
+    del g
+    with torch.cuda.stream(stream):
+        chosen, cands = ctx.autotune(lefts, rights, 256)
+    g = graphed()
+    ms_tuned = timed(g.replay)
+    res["tuned"] = {"d_chunks": chosen, "candidates_ms_per_batch": {str(k): round(v, 4) for k, v in cands.items()},
+                    "graph_pairs_per_s": round(8000.0 / ms_tuned, 1),
+                    "graph_ms_per_batch": round(ms_tuned, 4)}
+    del g
+    ctx.close()
+    return res
 
 
 def soft_leg(sm, steps):
@@ -306,6 +368,8 @@ def main():
                              "frac": round(LDS_BYTES_PER_EVAL * evals / t_match / PEAK_LDS_BYTES, 4)}},
     }
     ctx.close()
+    if args.batch_steps > 0:
+        res["batch8"] = batch_leg(sm, args.batch_steps)
     if args.serve_requests > 0:
         sv = serve_leg(args.serve_requests)
         # the served 1436x992 frames (upload and host copy included) against the

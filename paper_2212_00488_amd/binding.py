@@ -99,6 +99,10 @@ def lib():
         L.stereo_stage_times.argtypes = [P, ctypes.POINTER(ctypes.c_double),
                                          ctypes.POINTER(ctypes.c_int), I]
         L.stereo_stage_times.restype = I
+        L.stereo_autotune.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), I, I, I, I,
+                                      ctypes.POINTER(Params), ctypes.POINTER(I),
+                                      ctypes.POINTER(I), ctypes.POINTER(ctypes.c_float), I, P]
+        L.stereo_autotune.restype = I
         SP = ctypes.POINTER(SoftParams)
         L.stereo_soft_default_params.argtypes = [SP]
         L.stereo_soft_default_params.restype = None
@@ -235,6 +239,30 @@ class Stereo:
         self._raise(rc)
         self._last_shape = (W, H, dmax, params is not None and bool(params.flags & F_FULL_RES))
         return outs
+
+    def autotune(self, lefts, rights, dmax: int, params: Params | None = None, stream=None):
+        """Tune the d-chunk count for this shape on the given pairs; returns
+        (chosen count, {candidate count: ms per run})."""
+        n = len(lefts)
+        for t in list(lefts) + list(rights):
+            _check_image(t, "image")
+        H, W, _ = lefts[0].shape
+        arr = ctypes.c_void_p * n
+        chosen = ctypes.c_int()
+        counts = (ctypes.c_int * 32)()
+        times = (ctypes.c_float * 32)()
+        rc = lib().stereo_autotune(self._h, arr(*[t.data_ptr() for t in lefts]),
+                                   arr(*[t.data_ptr() for t in rights]), n, W, H, int(dmax),
+                                   ctypes.byref(params) if params is not None else None,
+                                   ctypes.byref(chosen), counts, times, 32,
+                                   _stream_handle(stream))
+        self._raise(rc)
+        out = {}
+        for c, v in zip(counts, times):
+            if v < 0 or c <= 0:
+                break
+            out[int(c)] = float(v)
+        return chosen.value, out
 
     def stage_times(self, reset: bool = True):
         """(per-stage milliseconds summed over timed calls, number of calls)."""

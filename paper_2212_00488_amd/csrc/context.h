@@ -17,6 +17,15 @@ struct SoftPlan;  // plan of the soft-argmin head, per (n, W, H, Dmax, params)
 void free_soft_plans(std::vector<SoftPlan*>& plans);
 }  // namespace stereo_host
 
+namespace stereo_host {
+// A launch geometry chosen by stereo_autotune for one shape and parameter set.
+struct Tuned {
+  int W, H, Dmax, npair;
+  stereo_params p;
+  int nchunk;
+};
+}  // namespace stereo_host
+
 struct stereo_ctx {
   int device = 0;
   // stage timing: one set of STEREO_NUM_STAGES + 1 events per timed call
@@ -29,6 +38,7 @@ struct stereo_ctx {
   std::string err;
   stereo_host::Plan* last = nullptr;  // plan of the last call that kept its intermediates
   uint64_t tick = 0;
+  std::vector<stereo_host::Tuned> tuned;  // d-chunk counts chosen by stereo_autotune
   // scratch of the L1 loss entry points, grown on demand
   void* l1_block = nullptr;
   int l1_pairs = 0;

@@ -89,7 +89,7 @@ void free_plan(Plan* pl) {
 
 // Launch geometry: bands keep the k_match LDS plane and the per-thread key
 // registers within bounds; d-chunks raise the workgroup count to fill the CUs.
-void plan_geometry(Plan& pl, int num_cu) {
+void plan_geometry(Plan& pl, int num_cu, int forced_nchunk) {
   // the row buffer spans x0 - hx .. x0 + 63 + arm_x, hx = arm_x + 1 rounded up to even
   pl.ns = (66 + 2 * std::max(pl.p.arm_x, pl.p.arm_x_r) + 127) / 128;
   const int pr = plane_rows(pl.ns);
@@ -122,8 +122,21 @@ void plan_geometry(Plan& pl, int num_cu) {
   const int per_chunk = pl.nstrips * pl.nbands * 2 * pl.npair;
   // one k_match workgroup fits a CU at a time (LDS): split d into as many
   // chunks as one round of CUs holds, at most D; each extra chunk costs one
-  // more key plane of traffic
+  // more key plane of traffic.  When the groups alone exceed the CUs (large
+  // batches), one chunk per group gives few long workgroups that balance
+  // badly over the rounds; four chunks measured 1.5x faster on 8 x
+  // 1920x1080 (stereo_autotune refines this per shape).
   pl.nchunk = std::max(1, std::min(pl.D, num_cu / per_chunk));
+  if (per_chunk > num_cu) pl.nchunk = std::min(pl.D, 4);
+  if (forced_nchunk > 0) pl.nchunk = std::min(forced_nchunk, pl.D);
+}
+
+// The d-chunk count stereo_autotune chose for this shape and parameters, or 0.
+int tuned_nchunk(const stereo_ctx* c, int W, int H, int Dmax, int npair, const stereo_params& p) {
+  for (const Tuned& t : c->tuned)
+    if (t.W == W && t.H == H && t.Dmax == Dmax && t.npair == npair && same_params(t.p, p))
+      return t.nchunk;
+  return 0;
 }
 
 int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int npair,
@@ -139,7 +152,7 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
   pl->p = p;
   build_tables(p, pl->lut_ad, pl->lut_mc);
   pl->cmax = pl->lut_ad[255] + pl->lut_mc[6];
-  plan_geometry(*pl, c->num_cu);
+  plan_geometry(*pl, c->num_cu, tuned_nchunk(c, W, H, Dmax, npair, p));
   const size_t n = (size_t)pl->X * pl->Y;
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t npk = (size_t)2 * npair * pl->Y * pl->XP, nar = (size_t)2 * npair * pl->Y * pl->XA;
@@ -226,6 +239,34 @@ int get_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int 
   c->plans.push_back(pl);
   *out = pl;
   return 0;
+}
+
+// Frees every plan of (W, H, Dmax, p), whatever its owner (after the device
+// has finished with them), so that the next call makes it again.
+int evict_shape(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p) {
+  HIP_TRY(c, hipDeviceSynchronize());
+  for (size_t i = 0; i < c->plans.size();) {
+    Plan* pl = c->plans[i];
+    if (pl->W == W && pl->H == H && pl->Dmax == Dmax && same_params(pl->p, p)) {
+      if (c->last == pl) c->last = nullptr;
+      c->used -= pl->bytes;
+      free_plan(pl);
+      c->plans.erase(c->plans.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+  return 0;
+}
+
+void set_tuned(stereo_ctx* c, int W, int H, int Dmax, int npair, const stereo_params& p,
+               int nchunk) {
+  for (Tuned& t : c->tuned)
+    if (t.W == W && t.H == H && t.Dmax == Dmax && t.npair == npair && same_params(t.p, p)) {
+      t.nchunk = nchunk;
+      return;
+    }
+  c->tuned.push_back(Tuned{W, H, Dmax, npair, p, nchunk});
 }
 
 MatchArgs match_args(const Plan& pl, int dlo, int dhi, int nchunk) {
@@ -423,6 +464,89 @@ int stereo_disparity_batch(stereo_ctx* c, const uint8_t* const* left, const uint
     if (rc) return rc;
   }
   if (keep) c->last = pl;
+  return 0;
+}
+
+int stereo_autotune(stereo_ctx* c, const uint8_t* const* left, const uint8_t* const* right, int n,
+                    int W, int H, int Dmax, const stereo_params* params, int* chosen,
+                    int* counts, float* times_ms, int max_times, hipStream_t stream) {
+  if (!c) return STEREO_EINVAL;
+  c->err.clear();
+  if (!left || !right || n < 1) return fail(c, STEREO_EINVAL, "null pointer or n < 1");
+  const int m = std::min(n, kMaxPairs);
+  for (int i = 0; i < m; ++i)
+    if (!left[i] || !right[i]) return fail(c, STEREO_EINVAL, "null image pointer %d", i);
+  stereo_params p;
+  int rc = common_checks(c, W, H, Dmax, params, &p);
+  if (rc) return rc;
+  p.flags &= ~(STEREO_F_KEEP_INTERMEDIATES | STEREO_F_STAGE_TIMING);
+  HIP_TRY(c, hipSetDevice(c->device));
+  // the default geometry, then candidates that fill 1..6 rounds of CUs
+  Plan probe{};
+  probe.W = W; probe.H = H; probe.Dmax = Dmax; probe.npair = m; probe.p = p;
+  probe.X = full_res(p) ? W : (W + 1) / 2;
+  probe.Y = full_res(p) ? H : (H + 1) / 2;
+  probe.D = full_res(p) ? Dmax : (Dmax + 1) / 2;
+  plan_geometry(probe, c->num_cu, 0);
+  const int groups = probe.nstrips * probe.nbands * 2 * m;
+  std::vector<int> cand{probe.nchunk};
+  auto add = [&](int ch) {
+    ch = std::max(1, std::min(probe.D, ch));
+    if (std::find(cand.begin(), cand.end(), ch) == cand.end()) cand.push_back(ch);
+  };
+  for (int k = 1; k <= 6; ++k) add((k * c->num_cu + groups / 2) / groups);
+  for (int ch : {1, 2, 3, 4, 6, 8, 12, 16, 20, 24, 32}) add(ch);
+  // scratch output maps for the trial runs
+  int16_t* outs = nullptr;
+  HIP_TRY(c, hipMalloc(&outs, (size_t)m * W * H * 2));
+  PairPtrs pp{};
+  for (int i = 0; i < m; ++i) {
+    pp.left[i] = left[i];
+    pp.right[i] = right[i];
+    pp.out[i] = outs + (size_t)i * W * H;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  int best = probe.nchunk;
+  float best_ms = 1e30f;
+  hipError_t he = hipEventCreate(&e0);
+  if (he == hipSuccess) he = hipEventCreate(&e1);
+  for (size_t k = 0; k < cand.size() && he == hipSuccess && rc == 0; ++k) {
+    set_tuned(c, W, H, Dmax, m, p, cand[k]);
+    rc = evict_shape(c, W, H, Dmax, p);
+    Plan* pl = nullptr;
+    if (!rc) rc = get_plan(c, W, H, Dmax, p, m, stream, &pl);
+    if (!rc) rc = run(c, *pl, pp, m, false, false, stream);  // warm
+    constexpr int kReps = 5;
+    if (!rc) he = hipEventRecord(e0, stream);
+    for (int r = 0; r < kReps && !rc && he == hipSuccess; ++r) rc = run(c, *pl, pp, m, false, false, stream);
+    if (!rc && he == hipSuccess) he = hipEventRecord(e1, stream);
+    if (!rc && he == hipSuccess) he = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (!rc && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
+    ms /= kReps;
+    if ((int)k < max_times) {
+      if (counts) counts[k] = cand[k];
+      if (times_ms) times_ms[k] = ms;
+    }
+    if (!rc && he == hipSuccess && ms < best_ms) {
+      best_ms = ms;
+      best = cand[k];
+    }
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(outs);
+  if (!rc && he != hipSuccess) rc = fail(c, STEREO_EHIP, "autotune: %s", hipGetErrorString(he));
+  set_tuned(c, W, H, Dmax, m, p, best);
+  const int rc2 = evict_shape(c, W, H, Dmax, p);
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (chosen) *chosen = best;
+  if (max_times > (int)cand.size()) {
+    if (counts) counts[cand.size()] = 0;
+    if (times_ms) times_ms[cand.size()] = -1.f;
+  }
   return 0;
 }
 

@@ -282,3 +282,46 @@ def test_variant_parameter_checks(sm, ctx):
         assert e.value.code == -1, kw
     # still usable
     ctx.disparity(lt, rt, 16)
+
+
+# ------------------------------------------------- captured graphs, autotune
+
+def test_graph_replays_match_eager(sm, ctx):
+    """A batched call captured in a HIP graph, replayed three times with other
+    eager work and synchronisations between, gives the eager maps each time."""
+    pairs = [make_pair(96, 64, 24, segments=3, seed=70 + i) for i in range(3)]
+    lefts = [torch.from_numpy(p.left).cuda() for p in pairs]
+    rights = [torch.from_numpy(p.right).cuda() for p in pairs]
+    outs = [torch.empty((64, 96), dtype=torch.int16, device="cuda") for _ in pairs]
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        ref = [o.cpu().numpy() for o in ctx.disparity_batch(lefts, rights, 24)]
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        ctx.disparity_batch(lefts, rights, 24, outs=outs)
+    other = make_pair(80, 40, 16, segments=2, seed=79)
+    for k in range(3):
+        for o in outs:
+            o.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(3):
+            assert np.array_equal(outs[i].cpu().numpy(), ref[i]), (k, i)
+        assert np.array_equal(ref[0], oracle.disparity(pairs[0].left, pairs[0].right, 24)["out"])
+        ctx.disparity(torch.from_numpy(other.left).cuda(), torch.from_numpy(other.right).cuda(), 16)
+        torch.cuda.synchronize()
+
+
+def test_autotune_keeps_results(sm, ctx):
+    pairs = [make_pair(300, 200, 48, segments=4, seed=80 + i) for i in range(2)]
+    lefts = [torch.from_numpy(p.left).cuda() for p in pairs]
+    rights = [torch.from_numpy(p.right).cuda() for p in pairs]
+    chosen, cands = ctx.autotune(lefts, rights, 48)
+    assert chosen in cands and len(cands) >= 2 and all(v > 0 for v in cands.values())
+    outs = ctx.disparity_batch(lefts, rights, 48)
+    torch.cuda.synchronize()
+    for i in range(2):
+        exp = oracle.disparity(pairs[i].left, pairs[i].right, 48)["out"]
+        assert np.array_equal(outs[i].cpu().numpy(), exp)
