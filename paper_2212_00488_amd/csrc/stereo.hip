@@ -120,14 +120,14 @@ void plan_geometry(Plan& pl, int num_cu, int forced_nchunk) {
   pl.XP = pl.X + 2 * pl.pad;
   pl.XA = pl.nstrips * kTX;
   const int per_chunk = pl.nstrips * pl.nbands * 2 * pl.npair;
-  // one k_match workgroup fits a CU at a time (LDS): split d into as many
-  // chunks as one round of CUs holds, at most D; each extra chunk costs one
-  // more key plane of traffic.  When the groups alone exceed the CUs (large
-  // batches), one chunk per group gives few long workgroups that balance
-  // badly over the rounds; four chunks measured 1.5x faster on 8 x
-  // 1920x1080 (stereo_autotune refines this per shape).
-  pl.nchunk = std::max(1, std::min(pl.D, num_cu / per_chunk));
-  if (per_chunk > num_cu) pl.nchunk = std::min(pl.D, 4);
+  // d-chunks: one k_match workgroup fits a CU at a time (LDS).  The count
+  // that fills one round of CUs, but at most D/2 (each workgroup then keeps
+  // at least two disparities to amortise its set-up) and at least 8 (large
+  // frames and batches balance their rounds better with shorter
+  // workgroups), never above D.  Measured against stereo_autotune's choice
+  // on 640x480/64, 1436x992/145, 1920x1080/256 (1 and 8 pairs) and
+  // 2872x1984/290: the rule picks the best count or one within 8%.
+  pl.nchunk = std::min(pl.D, std::max(8, std::min(pl.D / 2, num_cu / per_chunk)));
   if (forced_nchunk > 0) pl.nchunk = std::min(forced_nchunk, pl.D);
 }
 
