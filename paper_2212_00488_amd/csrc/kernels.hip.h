@@ -82,46 +82,54 @@ constexpr uint32_t kSentinel = 1022u;
 constexpr int kFeatRows = 16;    // output rows per k_feat workgroup (one pixel per thread)
 constexpr int kMaxArm = 127;
 
-// Grows the two arms of one axis for one pixel of value c: p points at the
-// pixel in an LDS tile, stride is the tile distance of one pixel step.  A
-// side grows by one while the next pixel satisfies |I - c| < delta and the
-// side is below its limit lim_* = min(cap, distance to the border).  Four
-// steps are evaluated per round (their eight LDS reads issued together) and
-// the rounds end once no lane of the wave can grow.
+// Length of one arm of a pixel of value c: the number of steps t = 1, 2, ...
+// along the axis, taken without a break, whose pixel satisfies |I - c| < delta,
+// at most lim.  p points at the pixel in an LDS tile and STRIDE is the tile
+// distance of one step (negative for the left / upper arm).  Steps are tested
+// in chunks of 32 into a bitmask, step t of a chunk in bit t-1, built from the
+// farthest step down so that each test is one add-with-carry; the chunk's run
+// is the number of trailing ones.  Steps are tested 4 at a time, so up to 3
+// steps past the cap are tested too: they only set bits above the cap, which
+// lim (<= cap) cuts off, and the tile holds kArmPad spare pixels for them.
+constexpr int kArmPad = 3;
+
+// m * 2 + [x < w]: the compare's lane bit enters as the carry of m + m
+__device__ __forceinline__ uint32_t shift_in_lt(uint32_t m, uint32_t x, uint32_t w) {
+  uint32_t r;
+  __asm__("v_cmp_gt_u32_e32 vcc, %2, %1\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc"
+          : "=v"(r) : "v"(x), "s"(w), "v"(m) : "vcc");
+  return r;
+}
+
 template <int STRIDE>
-__device__ __forceinline__ void grow_arms(const uint8_t* p, int c, int delta, int cap,
-                                          int lim_neg, int lim_pos, int& neg, int& pos) {
+__device__ __forceinline__ int arm_len(const uint8_t* p, int c, int delta, int cap, int lim) {
+  if (delta <= 0) return 0;
   // |v - c| < delta  <=>  (unsigned)(v + k) < w
-  const int k = delta - 1 - c;
+  uint32_t k = (uint32_t)(delta - 1 - c);
+  __asm__ volatile("" : "+v"(k));  // one per-lane operand: the test is add, compare
   const unsigned w = 2u * (unsigned)delta - 1u;
-  bool gn = delta > 0 && lim_neg > 0, gp = delta > 0 && lim_pos > 0;
-  neg = 0;
-  pos = 0;
-  for (int t0 = 1; t0 <= cap; t0 += 4) {
-    if (__builtin_amdgcn_ballot_w64(gn || gp) == 0) break;
-    int vn[4], vp[4];
+  int len = 0;
+  bool alive = true;
+  for (int c0 = 0; c0 < cap; c0 += 32) {
+    const int n4 = (min(32, cap - c0) + 3) & ~3;
+    uint32_t m = 0;
+    for (int u = n4; u > 0; u -= 4) {
+      const uint8_t* q = p + (c0 + u) * STRIDE;  // step c0 + u, then three nearer ones
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int tt = min(t0 + u, cap);
-      vn[u] = p[-tt * STRIDE];
-      vp[u] = p[tt * STRIDE];
+      for (int j = 0; j < 4; ++j) m = shift_in_lt(m, (uint32_t)q[-j * STRIDE] + k, w);
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int t = t0 + u;
-      gn = gn && t <= lim_neg && (unsigned)(vn[u] + k) < w;
-      gp = gp && t <= lim_pos && (unsigned)(vp[u] + k) < w;
-      neg += gn;
-      pos += gp;
-    }
+    const int run = m == 0xffffffffu ? 32 : __builtin_ctz(~m);
+    len += alive ? run : 0;
+    alive = alive && run == 32;
   }
+  return min(len, lim);
 }
 
 // One workgroup = 64 columns x kFeatRows rows of one image, one pixel per
 // thread.  Two LDS tiles of the half image (borders clamped): rows y0-1 ..
 // y0+kFeatRows over the columns reachable by the horizontal arms and the
 // census, and rows y0-arm_y .. y0+kFeatRows-1+arm_y over the 64 columns for
-// the vertical arms.
+// the vertical arms, each with kArmPad spare pixels past the arms.
 //   census: 6 neighbours in three rows, bit k = [neighbour < centre]
 //   arms  : contiguous pixels with |I - I(centre)| < delta, capped per side
 //           and at the image border; packed m | n<<8 | M<<16 | N<<24
@@ -131,22 +139,23 @@ __global__ void __launch_bounds__(64 * kFeatRows) k_feat(const uint8_t* __restri
                                                int XP, int pad,
                                                int XA, uint32_t* __restrict__ pk,
                                                uint32_t* __restrict__ arms) {
-  constexpr int TXW = 64 + 2 * (kMaxArm + 2);
+  constexpr int TXW = 64 + 2 * (kMaxArm + kArmPad);
   __shared__ uint8_t tx[kFeatRows + 2][TXW];
-  __shared__ uint8_t ty[kFeatRows + 2 * kMaxArm][64];
+  __shared__ uint8_t ty[kFeatRows + 2 * (kMaxArm + kArmPad)][64];
   const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kFeatRows, img = blockIdx.z;
   const uint8_t* h = half + (size_t)img * X * Y;
   // horizontal cap of this image (the two images may differ, Sec. V)
   const int arm_x = (img & 1) ? arm_x_r : arm_x_l;
-  const int hx = arm_x + 2, wx = 64 + 2 * hx;
+  // tile margins: the arms plus the spare steps (at least the census's 2)
+  const int hx = arm_x + kArmPad, wx = 64 + 2 * hx;
+  const int my = arm_y + kArmPad, hy = kFeatRows + 2 * my;
   for (int r = threadIdx.y; r < kFeatRows + 2; r += kFeatRows) {
     const uint8_t* src = h + (size_t)clampi(y0 - 1 + r, 0, Y - 1) * X;
     for (int c = threadIdx.x; c < wx; c += 64) tx[r][c] = src[clampi(x0 - hx + c, 0, X - 1)];
   }
-  const int hy = kFeatRows + 2 * arm_y;
   const int cx = clampi(x0 + (int)threadIdx.x, 0, X - 1);
   for (int r = threadIdx.y; r < hy; r += kFeatRows)
-    ty[r][threadIdx.x] = h[(size_t)clampi(y0 - arm_y + r, 0, Y - 1) * X + cx];
+    ty[r][threadIdx.x] = h[(size_t)clampi(y0 - my + r, 0, Y - 1) * X + cx];
   __syncthreads();
   const int lx = threadIdx.x, x = x0 + lx;
   if (x >= X) return;
@@ -162,9 +171,11 @@ __global__ void __launch_bounds__(64 * kFeatRows) k_feat(const uint8_t* __restri
     bits |= (row[2] < c) << 3;
     bits |= (tx[ly + 2][hx + lx - 1] < c) << 4;
     bits |= (tx[ly + 2][hx + lx + 1] < c) << 5;
-    int m, n, M, N;
-    grow_arms<1>(row, c, delta, arm_x, min(arm_x, x), min(arm_x, X - 1 - x), m, n);
-    grow_arms<64>(&ty[ly + arm_y][lx], c, delta, arm_y, min(arm_y, y), min(arm_y, Y - 1 - y), M, N);
+    const uint8_t* col = &ty[ly + my][lx];       // col[64 i] = I(x, y + i)
+    const int m = arm_len<-1>(row, c, delta, arm_x, min(arm_x, x));
+    const int n = arm_len<1>(row, c, delta, arm_x, min(arm_x, X - 1 - x));
+    const int M = arm_len<-64>(col, c, delta, arm_y, min(arm_y, y));
+    const int N = arm_len<64>(col, c, delta, arm_y, min(arm_y, Y - 1 - y));
     pk[((size_t)img * Y + y) * XP + pad + x] = (uint32_t)(2 * c) | ((uint32_t)bits << 16);
     arms[((size_t)img * Y + y) * XA + x] =
         (uint32_t)m | ((uint32_t)n << 8) | ((uint32_t)M << 16) | ((uint32_t)N << 24);
@@ -318,12 +329,15 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
     if (k & 1) marm[k / 2] |= mn << 16;
     else marm[k / 2] = mn;
   }
-  // plane word of (band row o0 + wave, column c); plane row = band row + 1
-  const int fin_base = (o0 + wave + 1) * 64 + c;
+  // byte offset in the plane of (band row o0 + wave, column c); plane row =
+  // band row + 1
+  const uint32_t fin_b = (uint32_t)((o0 + wave + 1) * 64 + c) * 4u;
   // the key shift lives in a VGPR, so that shift-and-or with the scalar d
   // is one instruction (one scalar operand per vector instruction)
   uint32_t vdbits = (uint32_t)a.dbits;
   __asm__ volatile("" : "+v"(vdbits));
+  uint32_t k8 = 8u;  // shift operand of the SDWA arm extraction below
+  __asm__ volatile("" : "+v"(k8));
   // byte offset of this lane's first column pair inside a padded pk row
   const uint32_t vb = (uint32_t)(a.pad + x0 - hx + 2 * lane) * 4u;
   __syncthreads();
@@ -439,16 +453,27 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
     // ---- vertical window and WTA for this wave's output rows
 #pragma unroll
     for (int j = 0; j < KMAX / 2; ++j) {
-      uint32_t mj = marm[j];
-      __asm__ volatile("" : "+v"(mj));  // keep the address math inside the d loop
+      // byte offsets of plane rows +N and -(M+1) from the output rows 2j and
+      // 2j+1: a plane row is 256 bytes, so each offset is one arm byte of
+      // marm[j] moved to bits 8..15, one SDWA instruction each.  Volatile
+      // asm keeps them inside the d loop (hoisted, they would need 64 VGPRs).
+      uint32_t off[4];
+      __asm__ volatile("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD "
+                       "src0_sel:DWORD src1_sel:BYTE_0" : "=v"(off[0]) : "v"(marm[j]), "v"(k8));
+      __asm__ volatile("v_and_b32 %0, 0xff00, %1" : "=v"(off[1]) : "v"(marm[j]));
+      __asm__ volatile("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD "
+                       "src0_sel:DWORD src1_sel:BYTE_2" : "=v"(off[2]) : "v"(marm[j]), "v"(k8));
+      __asm__ volatile("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD "
+                       "src0_sel:DWORD src1_sel:BYTE_3" : "=v"(off[3]) : "v"(marm[j]), "v"(k8));
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int k = 2 * j + h;
-        const int M = (mj >> (16 * h)) & 255u, N = (mj >> (16 * h + 8)) & 255u;
-        // per-lane part first; the per-row part k * 1024 words becomes the
-        // immediate offset of the LDS read
-        const int lo = fin_base - (M + 1) * 64, hi = fin_base + N * 64;
-        const uint32_t ca = s_plane[hi + k * kWaves * 64] - s_plane[lo + k * kWaves * 64];
+        // rows +N and -(M+1) of output row k (plane row 0 at least: M never
+        // reaches above the band); the per-row part k * 4096 bytes becomes
+        // the reads' immediate offset
+        const uint8_t* row = s_lds + kOffPlane + k * kWaves * 256 + fin_b;
+        const uint32_t ca = *reinterpret_cast<const uint32_t*>(row + off[2 * h + 1]) -
+                            *reinterpret_cast<const uint32_t*>(row - 256 - off[2 * h]);
         const uint32_t kv = (ca << vdbits) | (uint32_t)d;
         key[k] = kv < key[k] ? kv : key[k];
       }
