@@ -50,13 +50,33 @@ __global__ void __launch_bounds__(256) k_prep(PairPtrs pp, int W, int H, int X, 
   const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kPrepRows, img = blockIdx.z;
   const int pair = img >> 1;
   const uint8_t* rgb = (img & 1) ? pp.right[pair] : pp.left[pair];
-  const int t = threadIdx.y * 64 + threadIdx.x;
-  for (int r = threadIdx.y; r < TR; r += 4) {
+  // every tile pixel of this thread is loaded before the first is used, so
+  // that the loads overlap instead of each waiting for the previous one
+  constexpr int RPT = (TR + 3) / 4, CPT = (TC + 63) / 64;
+  uint32_t px[RPT][CPT][3];
+#pragma unroll
+  for (int i = 0; i < RPT; ++i) {
+    const int r = threadIdx.y + 4 * i;
     const uint8_t* row = rgb + (size_t)clampi(2 * y0 - 1 + r, 0, H - 1) * W * 3;
-    for (int c = threadIdx.x; c < TC; c += 64)
-      g[r][c] = (uint8_t)gray_of(row + (size_t)clampi(2 * x0 - 1 + c, 0, W - 1) * 3);
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      // rows and columns are clamped into the image, so positions past the
+      // tile load a valid pixel too (never stored): no branch between loads
+      const int c = threadIdx.x + 64 * j;
+      const uint8_t* q = row + (size_t)clampi(2 * x0 - 1 + c, 0, W - 1) * 3;
+      px[i][j][0] = q[0];
+      px[i][j][1] = q[1];
+      px[i][j][2] = q[2];
+    }
   }
-  (void)t;
+#pragma unroll
+  for (int i = 0; i < RPT; ++i)
+#pragma unroll
+    for (int j = 0; j < CPT; ++j) {
+      const int r = threadIdx.y + 4 * i, c = threadIdx.x + 64 * j;
+      if (r < TR && c < TC)
+        g[r][c] = (uint8_t)((77 * px[i][j][0] + 150 * px[i][j][1] + 29 * px[i][j][2] + 128) >> 8);
+    }
   __syncthreads();
   const int lx = threadIdx.x, x = x0 + lx;
   if (x >= X) return;
@@ -539,6 +559,9 @@ __global__ void __launch_bounds__(256) k_wta(const uint32_t* __restrict__ keys, 
 // a tie) (Sec. III-E).  One side only: copy it; none: 0.  fill_mode 1 and 2
 // are the two simpler fills Sec. III-E describes first: the GCP closer in
 // distance (the right one at equal distance), or the smaller disparity.
+// The rows are staged in LDS, the GCP flags of the row become a bit array
+// (one wave ballot per 64 columns), and each non-GCP finds its nearest GCPs
+// by bit search in that array.
 // grid: (Y, npair), block 256.
 __device__ __forceinline__ int floor_div_pos(int n, int d) {  // d > 0
   return n >= 0 ? n / d : -((-n + d - 1) / d);
@@ -555,69 +578,86 @@ __device__ __forceinline__ int median9(int* v) {
   return v[4];
 }
 
+constexpr int kRefMaxX = 4096;  // widest half-res (or full-res mode) row
+
 __global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp, int nk,
                                                 const uint32_t* __restrict__ pk, int XP, int pad,
                                                 int X, int Y, int T, int fill_mode,
                                                 uint8_t* __restrict__ gcp_out,
                                                 int16_t* __restrict__ med_out,
                                                 int16_t* __restrict__ filled) {
-  __shared__ int16_t s_med[4096];
-  __shared__ uint8_t s_g[4096];
-  __shared__ uint8_t s_h[4096];
-  __shared__ int16_t s_xl[4096];
-  __shared__ int s_lastg[256];
-  __shared__ int s_firstg[256];
+  __shared__ int16_t s_d[4][kRefMaxX];          // D^L rows y-1, y, y+1 (clamped), D^R row y
+  __shared__ int16_t s_med[kRefMaxX];
+  __shared__ uint8_t s_h[kRefMaxX];             // left gray of row y
+  __shared__ uint64_t s_gm[kRefMaxX / 64];      // GCP flag of column x in bit x % 64 of word x / 64
   const int y = blockIdx.x, pair = blockIdx.y, t = threadIdx.x;
   const size_t plane = (size_t)X * Y;
   const int16_t* dl = disp + (size_t)(2 * pair) * nk;
-  const int16_t* dr = disp + (size_t)(2 * pair + 1) * nk + (size_t)y * X;
-  const int ym = max(y - 1, 0), yp = min(y + 1, Y - 1);
+  const int16_t* dr = disp + (size_t)(2 * pair + 1) * nk;
+  const uint32_t* pkr = pk + ((size_t)(2 * pair) * Y + y) * XP + pad;
+  const size_t rm = (size_t)max(y - 1, 0) * X, r0 = (size_t)y * X, rp = (size_t)min(y + 1, Y - 1) * X;
+  // stage the rows: four columns per thread and round, all loads of a round
+  // issued before its stores (clamped columns load a valid value, not stored)
+  for (int xb = 0; xb < X; xb += 1024) {
+    int16_t a[4][4];
+    uint32_t hp[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int x = min(xb + t + 256 * i, X - 1);
+      a[i][0] = dl[rm + x];
+      a[i][1] = dl[r0 + x];
+      a[i][2] = dl[rp + x];
+      a[i][3] = dr[r0 + x];
+      hp[i] = pkr[x];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int x = xb + t + 256 * i;
+      if (x < X) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s_d[q][x] = a[i][q];
+        s_h[x] = (uint8_t)((hp[i] & 1023u) >> 1);
+      }
+    }
+  }
+  __syncthreads();
+  // cross-check and median; the GCP flags of 64 consecutive columns are one
+  // wave's ballot
+  for (int xb = 0; xb < X; xb += 256) {
+    const int x = xb + t;
+    bool g = false;
+    if (x < X) {
+      const int xm = max(x - 1, 0), xp = min(x + 1, X - 1);
+      int v[9] = {s_d[0][xm], s_d[0][x], s_d[0][xp], s_d[1][xm], s_d[1][x],
+                  s_d[1][xp], s_d[2][xm], s_d[2][x], s_d[2][xp]};
+      const int k = v[4];
+      g = x - k >= 0 && s_d[3][x - k] == k;
+      const int m = median9(v);
+      s_med[x] = (int16_t)m;
+      if (gcp_out) gcp_out[(size_t)pair * plane + r0 + x] = (uint8_t)g;
+      if (med_out) med_out[(size_t)pair * plane + r0 + x] = (int16_t)m;
+    }
+    const uint64_t bal = __ballot(g);
+    if ((t & 63) == 0) s_gm[x >> 6] = bal;
+  }
+  __syncthreads();
+  // fill: the nearest GCPs left and right from the bit array
+  const int nw = (X + 63) >> 6;
+  int16_t* fo = filled + (size_t)pair * plane + r0;
   for (int x = t; x < X; x += 256) {
-    const int xm = max(x - 1, 0), xp = min(x + 1, X - 1);
-    int v[9] = {dl[(size_t)ym * X + xm], dl[(size_t)ym * X + x], dl[(size_t)ym * X + xp],
-                dl[(size_t)y * X + xm],  dl[(size_t)y * X + x],  dl[(size_t)y * X + xp],
-                dl[(size_t)yp * X + xm], dl[(size_t)yp * X + x], dl[(size_t)yp * X + xp]};
-    const int k = v[4];
-    const uint8_t g = (uint8_t)(x - k >= 0 && dr[x - k] == k);
-    s_g[x] = g;
-    if (gcp_out) gcp_out[(size_t)pair * plane + (size_t)y * X + x] = g;
-    const int m = median9(v);
-    s_med[x] = (int16_t)m;
-    if (med_out) med_out[(size_t)pair * plane + (size_t)y * X + x] = (int16_t)m;
-    s_h[x] = (uint8_t)((pk[((size_t)(2 * pair) * Y + y) * XP + pad + x] & 1023u) >> 1);
-  }
-  __syncthreads();
-  // nearest GCP to the left / right: contiguous segments per thread + scans
-  const int cpt = (X + 255) / 256;
-  const int sx0 = min(t * cpt, X), sx1 = min(sx0 + cpt, X);
-  int lastg = -1, firstg = X;
-  for (int x = sx0; x < sx1; ++x)
-    if (s_g[x]) { lastg = x; if (firstg == X) firstg = x; }
-  s_lastg[t] = lastg;
-  s_firstg[t] = firstg;
-  __syncthreads();
-  for (int st = 1; st < 256; st <<= 1) {  // inclusive max-scan / reverse min-scan
-    const int a = t >= st ? s_lastg[t - st] : -1;
-    const int b = t + st < 256 ? s_firstg[t + st] : X;
-    __syncthreads();
-    s_lastg[t] = max(s_lastg[t], a);
-    s_firstg[t] = min(s_firstg[t], b);
-    __syncthreads();
-  }
-  int prev = t > 0 ? s_lastg[t - 1] : -1;
-  for (int x = sx0; x < sx1; ++x) {
-    s_xl[x] = (int16_t)prev;
-    if (s_g[x]) prev = x;
-  }
-  int next = t < 255 ? s_firstg[t + 1] : X;
-  int16_t* fo = filled + (size_t)pair * plane + (size_t)y * X;
-  for (int x = sx1 - 1; x >= sx0; --x) {
+    const int wx = x >> 6, bx = x & 63;
     int v;
-    if (s_g[x]) {
+    if ((s_gm[wx] >> bx) & 1ull) {
       v = s_med[x];
-      next = x;
     } else {
-      const int xl = s_xl[x], xr = next;
+      int w = wx, xl = -1, xr = X;
+      uint64_t mk = s_gm[w] & ((1ull << bx) - 1ull);            // columns < x
+      while (mk == 0ull && w > 0) mk = s_gm[--w];
+      if (mk) xl = w * 64 + 63 - __builtin_clzll(mk);
+      w = wx;
+      mk = bx == 63 ? 0ull : s_gm[w] & (~0ull << (bx + 1));     // columns > x
+      while (mk == 0ull && w + 1 < nw) mk = s_gm[++w];
+      if (mk) xr = w * 64 + __builtin_ctzll(mk);
       if (xl >= 0 && xr < X) {
         const int i = x - xl, j = xr - x, dla = s_med[xl], drb = s_med[xr];
         if (fill_mode == 1) {
@@ -671,6 +711,8 @@ __global__ void __launch_bounds__(256) k_copy_out(PairPtrs pp, const int16_t* __
 // a tie); a last odd column copies.  Along y: odd rows are the rounded-up
 // mean of the two neighbouring upscaled rows; a last odd row copies.
 // grid: (ceil(X/64), ceil(Y/4), npair), block (64, 4).
+// odd column between upscaled values 2*dlv and 2*drv; g0, g1, g2 are the
+// full-res grays left of, at and right of it
 __device__ __forceinline__ int up_odd(int dlv, int drv, const uint8_t* rgb_row, int xo, int T) {
   if (iabs(dlv - drv) <= T) return dlv + drv;
   const int g0 = gray_of(rgb_row + (xo - 1) * 3), g1 = gray_of(rgb_row + xo * 3),
