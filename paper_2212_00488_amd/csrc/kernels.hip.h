@@ -533,13 +533,32 @@ __global__ void __launch_bounds__(256) k_wta(const uint32_t* __restrict__ keys, 
   const int pair = blockIdx.y;
   if (i >= nk) return;
   const uint32_t* kp = keys + (size_t)pair * nchunk * 2 * nk + i;
+  // chunks in groups of kWtaGroup, all loads of a group (both bases) in
+  // flight together; a group running past the last chunk reloads the last
+  // one, which leaves the minimum unchanged
+  constexpr int kWtaGroup = 8;
+  u32x4 mb[2];
+  mb[0] = mb[1] = u32x4{0xffffffffu, 0xffffffffu, 0xffffffffu, 0xffffffffu};
+  for (int c0 = 0; c0 < nchunk; c0 += kWtaGroup) {
+    u32x4 v[kWtaGroup][2];
+#pragma unroll
+    for (int g = 0; g < kWtaGroup; ++g) {
+      const int c = min(c0 + g, nchunk - 1);
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        v[g][b] = *reinterpret_cast<const u32x4*>(kp + ((size_t)c * 2 + b) * nk);
+    }
+#pragma unroll
+    for (int g = 0; g < kWtaGroup; ++g)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        mb[b].x = min(mb[b].x, v[g][b].x); mb[b].y = min(mb[b].y, v[g][b].y);
+        mb[b].z = min(mb[b].z, v[g][b].z); mb[b].w = min(mb[b].w, v[g][b].w);
+      }
+  }
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
-    u32x4 m = *reinterpret_cast<const u32x4*>(kp + (size_t)b * nk);
-    for (int c = 1; c < nchunk; ++c) {
-      const u32x4 v = *reinterpret_cast<const u32x4*>(kp + ((size_t)c * 2 + b) * nk);
-      m.x = min(m.x, v.x); m.y = min(m.y, v.y); m.z = min(m.z, v.z); m.w = min(m.w, v.w);
-    }
+    const u32x4 m = mb[b];
     const size_t o = (size_t)(2 * pair + b) * nk + i;
     const uint32_t dm = (1u << dbits) - 1u;
     *reinterpret_cast<i16x4*>(disp + o) =
