@@ -127,7 +127,7 @@ def cpu_baseline(pair, seconds):
 def batch_leg(sm, steps):
     """8 synthetic 1920x1080 pairs, Dmax = 256 (seeds 300-307), one batched
     call per step: eager launches, the same call replayed from a captured HIP
-    graph, and the graph again after stereo_autotune picked the d-chunk count
+    graph, and the graph again after stereo_autotune picked the d-chunk size
     of the fused kernel.  Pairs per second for each."""
     import torch
     from paper_2212_00488_amd.synth import workload_pairs
@@ -176,7 +176,7 @@ def batch_leg(sm, steps):
         chosen, cands = ctx.autotune(lefts, rights, 256)
     g = graphed()
     ms_tuned = timed(g.replay)
-    res["tuned"] = {"d_chunks": chosen, "candidates_ms_per_batch": {str(k): round(v, 4) for k, v in cands.items()},
+    res["tuned"] = {"d_chunk_size": chosen, "candidates_ms_per_batch": {str(k): round(v, 4) for k, v in cands.items()},
                     "graph_pairs_per_s": round(8000.0 / ms_tuned, 1),
                     "graph_ms_per_batch": round(ms_tuned, 4)}
     del g

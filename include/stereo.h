@@ -120,19 +120,19 @@ int stereo_disparity_batch(stereo_ctx* ctx, const uint8_t* const* left,
                            hipStream_t stream);
 
 /* Tunes the launch geometry of the fused cost / aggregation / WTA kernel for
- * one shape: times candidate counts of disparity chunks (the default,
- * counts that fill 1..6 rounds of compute units, and 1, 2, 3, 4, 6, 8, 12,
- * 16, 20, 24, 32, each at most the range D) on the caller's min(n, 8)
- * pairs (device images as for stereo_disparity_batch), five runs each, and
- * keeps the fastest for later calls on this context with the same W, H,
- * Dmax, pair count and params; results do not depend on it.  *chosen (may
- * be NULL) receives the count; counts and times_ms (each may be NULL,
- * max_times entries, host memory) the candidates in trial order and their
- * average milliseconds per run, followed by 0 / -1 when room is left.
- * Synchronises the device; frees and re-makes the shape's scratch. */
+ * one shape: times candidate sizes of its disparity chunks (the default the
+ * library's scheduling model picks, then ceil(D / k) for k = 1 .. min(D, 32))
+ * on the caller's min(n, 8) pairs (device images as for
+ * stereo_disparity_batch), five runs each, and keeps the fastest for later
+ * calls on this context with the same W, H, Dmax, pair count and params;
+ * results do not depend on it.  *chosen (may be NULL) receives the size in
+ * disparities; sizes and times_ms (each may be NULL, max_times entries, host
+ * memory) the candidates in trial order and their average milliseconds per
+ * run, followed by 0 / -1 when room is left.  Synchronises the device; frees
+ * and re-makes the shape's scratch. */
 int stereo_autotune(stereo_ctx* ctx, const uint8_t* const* left, const uint8_t* const* right,
                     int n, int W, int H, int Dmax, const stereo_params* params, int* chosen,
-                    int* counts, float* times_ms, int max_times, hipStream_t stream);
+                    int* sizes, float* times_ms, int max_times, hipStream_t stream);
 
 /* Debug export of one plane of the last stereo_disparity call made with
  * STEREO_F_KEEP_INTERMEDIATES (pair 0 of a batch).  Copies into HOST memory

@@ -241,8 +241,8 @@ class Stereo:
         return outs
 
     def autotune(self, lefts, rights, dmax: int, params: Params | None = None, stream=None):
-        """Tune the d-chunk count for this shape on the given pairs; returns
-        (chosen count, {candidate count: ms per run})."""
+        """Tune the d-chunk size of the fused kernel for this shape on the
+        given pairs; returns (chosen size, {candidate size: ms per run})."""
         n = len(lefts)
         for t in list(lefts) + list(rights):
             _check_image(t, "image")

@@ -22,7 +22,7 @@ namespace stereo_host {
 struct Tuned {
   int W, H, Dmax, npair;
   stereo_params p;
-  int nchunk;
+  int csize;  // disparities per k_match d-chunk
 };
 }  // namespace stereo_host
 

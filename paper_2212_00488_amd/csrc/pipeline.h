@@ -17,7 +17,8 @@ struct Plan {
   uint16_t lut_ad[256]{}, lut_mc[7]{};
   int cmax = 0;
   int dbits = 8;                // bits of d in the WTA keys
-  int ns = 1, kmax = 8, nstrips = 0, nbands = 0, nchunk = 0;
+  int ns = 1, kmax = 8, nstrips = 0, nbands = 0;
+  int csize = 1, nchunk = 0;    // k_match d-chunk size and chunk count ceil(D / csize)
   int XP = 0, pad = 0, XA = 0;  // padded pitches of pk and arms
   int nk = 0;                   // padded plane stride of keys, disp and mincost
   size_t bytes = 0;

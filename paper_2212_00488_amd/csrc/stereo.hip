@@ -87,9 +87,75 @@ void free_plan(Plan* pl) {
 }
 
 
+// Modelled k_match time, in units of one disparity of one workgroup, for
+// d-chunks of cs disparities: each XCD's workgroups, in k_match's order of
+// positions, go to dispatch queue (position % kXcdQueues), where each takes
+// the CU of that queue that frees first; a workgroup costs its disparities
+// plus ovh units of set-up and drain (cost table, arms, key stores).
+// Remainder chunks are placed as k_match places them.  The queue structure
+// (4 queues of 8 CUs per XCD, filled in turn) is what measurement of these
+// placements shows: a workgroup past the first round waits for a CU of its
+// own queue, not for the first CU to free.
+double match_makespan(int groups, int D, int cs, int cus_per_xcd, double ovh) {
+  const int nfull = D / cs, rem = D - nfull * cs, nchunk = nfull + (rem > 0);
+  const int nloc = (groups + kXcds - 1) / kXcds, T = nloc * nchunk;
+  const int per_q = std::max(1, cus_per_xcd / kXcdQueues);
+  const bool stacked = nchunk != nfull && kXcdQueues * (nloc - 1) <= T - 1;
+  double worst = 0.0;
+  std::vector<double> cu((size_t)kXcdQueues * per_q);
+  for (int x = 0; x < kXcds && x < groups; ++x) {
+    std::fill(cu.begin(), cu.end(), 0.0);
+    for (int j = 0; j < T; ++j) {
+      int local, chunk;
+      const int q = T - 1 - j;
+      if (stacked && q % kXcdQueues == 0 && q / kXcdQueues < nloc) {
+        local = nloc - 1 - q / kXcdQueues;
+        chunk = nfull;
+      } else if (stacked) {
+        const int i = j - std::max(0, nloc - (q / kXcdQueues + 1));
+        local = i / nfull;
+        chunk = i - local * nfull;
+      } else {
+        local = j < nloc * nfull ? j / nfull : j - nloc * nfull;
+        chunk = j < nloc * nfull ? j - local * nfull : nfull;
+      }
+      if (local * kXcds + x >= groups) continue;  // padding workgroup
+      double* qb = cu.data() + (size_t)(j % kXcdQueues) * per_q;
+      *std::min_element(qb, qb + per_q) += ovh + (chunk < nfull ? cs : rem);
+    }
+    worst = std::max(worst, *std::max_element(cu.begin(), cu.end()));
+  }
+  return worst;
+}
+
+// Chunk size with the shortest modelled time among ceil(D / n), n = 1..64,
+// at most 16 workgroups per CU.  A workgroup's fixed cost (set-up, drain and
+// the first disparity's cold reads) is taken as one disparity over
+// kSetupRows band rows: fitted to timings of all chunk sizes at 640x480,
+// 1436x992, 1920x1080 (1 and 8 pairs) and 2872x1984, where this value picks
+// the fastest size or one within 6% of it.
+constexpr double kSetupRows = 300.0;
+
+int best_chunk_size(int groups, int D, int rows, int num_cu) {
+  const int cus = std::max(1, num_cu / kXcds);
+  const double ovh = kSetupRows / std::max(1, rows);
+  int best = D;
+  double best_t = 1e300;
+  for (int n = 1; n <= std::min(D, 64); ++n) {
+    const int cs = (D + n - 1) / n;
+    if ((long)groups * ((D + cs - 1) / cs) > 16L * num_cu) break;
+    const double t = match_makespan(groups, D, cs, cus, ovh);
+    if (t < best_t - 1e-9) {  // ties keep the larger chunks (fewer workgroups)
+      best_t = t;
+      best = cs;
+    }
+  }
+  return best;
+}
+
 // Launch geometry: bands keep the k_match LDS plane and the per-thread key
 // registers within bounds; d-chunks raise the workgroup count to fill the CUs.
-void plan_geometry(Plan& pl, int num_cu, int forced_nchunk) {
+void plan_geometry(Plan& pl, int num_cu, int forced_csize) {
   // the row buffer spans x0 - hx .. x0 + 63 + arm_x, hx = arm_x + 1 rounded up to even
   pl.ns = (66 + 2 * std::max(pl.p.arm_x, pl.p.arm_x_r) + 127) / 128;
   const int pr = plane_rows(pl.ns);
@@ -119,23 +185,19 @@ void plan_geometry(Plan& pl, int num_cu, int forced_nchunk) {
   pl.pad = ((128 * pl.ns + pl.D + 2) + 3) & ~3;
   pl.XP = pl.X + 2 * pl.pad;
   pl.XA = pl.nstrips * kTX;
-  const int per_chunk = pl.nstrips * pl.nbands * 2 * pl.npair;
-  // d-chunks: one k_match workgroup fits a CU at a time (LDS).  The count
-  // that fills one round of CUs, but at most D/2 (each workgroup then keeps
-  // at least two disparities to amortise its set-up) and at least 8 (large
-  // frames and batches balance their rounds better with shorter
-  // workgroups), never above D.  Measured against stereo_autotune's choice
-  // on 640x480/64, 1436x992/145, 1920x1080/256 (1 and 8 pairs) and
-  // 2872x1984/290: the rule picks the best count or one within 8%.
-  pl.nchunk = std::min(pl.D, std::max(8, std::min(pl.D / 2, num_cu / per_chunk)));
-  if (forced_nchunk > 0) pl.nchunk = std::min(forced_nchunk, pl.D);
+  const int groups = pl.nstrips * pl.nbands * 2 * pl.npair;
+  // d-chunks of csize disparities (the last one the remainder): the size
+  // with the shortest modelled k_match time, or the one stereo_autotune chose
+  const int rows = pl.nbands == 1 ? pl.Y : std::min(pl.Y, (pl.Y + pl.nbands - 1) / pl.nbands + 2 * pl.p.arm_y);
+  pl.csize = forced_csize > 0 ? std::min(forced_csize, pl.D) : best_chunk_size(groups, pl.D, rows, num_cu);
+  pl.nchunk = (pl.D + pl.csize - 1) / pl.csize;
 }
 
-// The d-chunk count stereo_autotune chose for this shape and parameters, or 0.
-int tuned_nchunk(const stereo_ctx* c, int W, int H, int Dmax, int npair, const stereo_params& p) {
+// The d-chunk size stereo_autotune chose for this shape and parameters, or 0.
+int tuned_csize(const stereo_ctx* c, int W, int H, int Dmax, int npair, const stereo_params& p) {
   for (const Tuned& t : c->tuned)
     if (t.W == W && t.H == H && t.Dmax == Dmax && t.npair == npair && same_params(t.p, p))
-      return t.nchunk;
+      return t.csize;
   return 0;
 }
 
@@ -152,7 +214,7 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
   pl->p = p;
   build_tables(p, pl->lut_ad, pl->lut_mc);
   pl->cmax = pl->lut_ad[255] + pl->lut_mc[6];
-  plan_geometry(*pl, c->num_cu, tuned_nchunk(c, W, H, Dmax, npair, p));
+  plan_geometry(*pl, c->num_cu, tuned_csize(c, W, H, Dmax, npair, p));
   const size_t n = (size_t)pl->X * pl->Y;
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t npk = (size_t)2 * npair * pl->Y * pl->XP, nar = (size_t)2 * npair * pl->Y * pl->XA;
@@ -260,23 +322,25 @@ int evict_shape(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p) {
 }
 
 void set_tuned(stereo_ctx* c, int W, int H, int Dmax, int npair, const stereo_params& p,
-               int nchunk) {
+               int csize) {
   for (Tuned& t : c->tuned)
     if (t.W == W && t.H == H && t.Dmax == Dmax && t.npair == npair && same_params(t.p, p)) {
-      t.nchunk = nchunk;
+      t.csize = csize;
       return;
     }
-  c->tuned.push_back(Tuned{W, H, Dmax, npair, p, nchunk});
+  c->tuned.push_back(Tuned{W, H, Dmax, npair, p, csize});
 }
 
-MatchArgs match_args(const Plan& pl, int dlo, int dhi, int nchunk) {
+MatchArgs match_args(const Plan& pl, int dlo, int dhi, int csize) {
   MatchArgs a{};
   a.pk = pl.pk; a.arms = pl.arms; a.tab = pl.tab; a.keys = pl.keys;
   a.X = pl.X; a.Y = pl.Y; a.XP = pl.XP; a.pad = pl.pad; a.XA = pl.XA; a.nk = pl.nk;
   a.arm_x = pl.p.arm_x; a.arm_x_r = pl.p.arm_x_r; a.arm_y = pl.p.arm_y; a.dbits = pl.dbits;
   a.pk_bytes = (uint32_t)((size_t)2 * pl.npair * pl.Y * pl.XP * 4);
   a.arms_bytes = (uint32_t)((size_t)2 * pl.npair * pl.Y * pl.XA * 4);
-  a.nbands = pl.nbands; a.nchunk = nchunk; a.dlo = dlo; a.dhi = dhi;
+  a.nbands = pl.nbands; a.dlo = dlo; a.dhi = dhi;
+  a.csize = std::max(1, std::min(csize, dhi - dlo));
+  a.nchunk = (dhi - dlo + a.csize - 1) / a.csize;
   return a;
 }
 
@@ -340,7 +404,7 @@ int run(stereo_ctx* c, Plan& pl, const PairPtrs& pp, int npair, bool keep, bool 
                      s, pl.half, X, Y, pl.p.color_delta, pl.p.arm_x, pl.p.arm_x_r, pl.p.arm_y,
                      pl.XP, pl.pad, pl.XA, pl.pk, pl.arms);
   mark(2);
-  launch_match(pl, match_args(pl, 0, pl.D, pl.nchunk), npair, s);
+  launch_match(pl, match_args(pl, 0, pl.D, pl.csize), npair, s);
   mark(3);
   hipLaunchKernelGGL(k_wta, dim3((pl.nk + 1023) / 1024, npair), dim3(256), 0, s, pl.keys,
                      pl.nchunk, pl.nk, pl.dbits, pl.disp, keep ? pl.mincost : nullptr);
@@ -469,7 +533,7 @@ int stereo_disparity_batch(stereo_ctx* c, const uint8_t* const* left, const uint
 
 int stereo_autotune(stereo_ctx* c, const uint8_t* const* left, const uint8_t* const* right, int n,
                     int W, int H, int Dmax, const stereo_params* params, int* chosen,
-                    int* counts, float* times_ms, int max_times, hipStream_t stream) {
+                    int* sizes, float* times_ms, int max_times, hipStream_t stream) {
   if (!c) return STEREO_EINVAL;
   c->err.clear();
   if (!left || !right || n < 1) return fail(c, STEREO_EINVAL, "null pointer or n < 1");
@@ -481,21 +545,18 @@ int stereo_autotune(stereo_ctx* c, const uint8_t* const* left, const uint8_t* co
   if (rc) return rc;
   p.flags &= ~(STEREO_F_KEEP_INTERMEDIATES | STEREO_F_STAGE_TIMING);
   HIP_TRY(c, hipSetDevice(c->device));
-  // the default geometry, then candidates that fill 1..6 rounds of CUs
+  // the modelled default, then sizes ceil(D / k), k = 1 .. min(D, 32)
   Plan probe{};
   probe.W = W; probe.H = H; probe.Dmax = Dmax; probe.npair = m; probe.p = p;
   probe.X = full_res(p) ? W : (W + 1) / 2;
   probe.Y = full_res(p) ? H : (H + 1) / 2;
   probe.D = full_res(p) ? Dmax : (Dmax + 1) / 2;
   plan_geometry(probe, c->num_cu, 0);
-  const int groups = probe.nstrips * probe.nbands * 2 * m;
-  std::vector<int> cand{probe.nchunk};
-  auto add = [&](int ch) {
-    ch = std::max(1, std::min(probe.D, ch));
-    if (std::find(cand.begin(), cand.end(), ch) == cand.end()) cand.push_back(ch);
-  };
-  for (int k = 1; k <= 6; ++k) add((k * c->num_cu + groups / 2) / groups);
-  for (int ch : {1, 2, 3, 4, 6, 8, 12, 16, 20, 24, 32}) add(ch);
+  std::vector<int> cand{probe.csize};
+  for (int k = 1; k <= std::min(probe.D, 32); ++k) {
+    const int cs = (probe.D + k - 1) / k;
+    if (std::find(cand.begin(), cand.end(), cs) == cand.end()) cand.push_back(cs);
+  }
   // scratch output maps for the trial runs
   int16_t* outs = nullptr;
   HIP_TRY(c, hipMalloc(&outs, (size_t)m * W * H * 2));
@@ -506,7 +567,7 @@ int stereo_autotune(stereo_ctx* c, const uint8_t* const* left, const uint8_t* co
     pp.out[i] = outs + (size_t)i * W * H;
   }
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  int best = probe.nchunk;
+  int best = probe.csize;
   float best_ms = 1e30f;
   hipError_t he = hipEventCreate(&e0);
   if (he == hipSuccess) he = hipEventCreate(&e1);
@@ -525,7 +586,7 @@ int stereo_autotune(stereo_ctx* c, const uint8_t* const* left, const uint8_t* co
     if (!rc && he == hipSuccess) he = hipEventElapsedTime(&ms, e0, e1);
     ms /= kReps;
     if ((int)k < max_times) {
-      if (counts) counts[k] = cand[k];
+      if (sizes) sizes[k] = cand[k];
       if (times_ms) times_ms[k] = ms;
     }
     if (!rc && he == hipSuccess && ms < best_ms) {
@@ -544,7 +605,7 @@ int stereo_autotune(stereo_ctx* c, const uint8_t* const* left, const uint8_t* co
   if (rc2) return rc2;
   if (chosen) *chosen = best;
   if (max_times > (int)cand.size()) {
-    if (counts) counts[cand.size()] = 0;
+    if (sizes) sizes[cand.size()] = 0;
     if (times_ms) times_ms[cand.size()] = -1.f;
   }
   return 0;
