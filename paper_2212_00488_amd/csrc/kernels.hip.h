@@ -38,46 +38,72 @@ __device__ __forceinline__ int gray_of(const uint8_t* p) {
 
 // ---------------------------------------------------------------- k_prep
 // One workgroup = 64 x 8 half-res pixels of one image.  The gray values of
-// the full-res rows 2 y0 - 1 .. 2 y0 + 15 and columns 2 x0 - 1 .. 2 x0 + 128
+// the full-res rows 2 y0 - 1 .. 2 y0 + 15 and columns 2 x0 - 4 .. 2 x0 + 131
 // (borders clamped) go to LDS; each thread then forms the rounded-half-up
-// mean of the 3x3 block centred on (2x, 2y) for two output rows.
+// mean of the 3x3 block centred on (2x, 2y) for two output rows.  Where the
+// tile's columns lie inside the image, rows start 4-byte aligned (W a
+// multiple of 4, aligned base) and a thread reads 4 RGB pixels as three
+// aligned words; each gray is then one byte-align and one 4-byte dot product.
+// Elsewhere each pixel is read bytewise with clamped coordinates.
 // grid: (ceil(X/64), ceil(Y/8), 2 * npair), block (64, 4).
 constexpr int kPrepRows = 8;
 
 __global__ void __launch_bounds__(256) k_prep(PairPtrs pp, int W, int H, int X, int Y,
                                               uint8_t* __restrict__ half) {
-  constexpr int TR = 2 * kPrepRows + 1, TC = 130;
-  __shared__ uint8_t g[TR][TC];
+  constexpr int TR = 2 * kPrepRows + 1, TC = 136, TG = TC / 4;  // TG groups of 4 pixels a row
+  constexpr uint32_t kGrayW = 77u | 150u << 8 | 29u << 16;      // gray weights per byte
+  __shared__ __align__(4) uint8_t g[TR + 1][TC];  // row TR takes the stores of idle items
   const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kPrepRows, img = blockIdx.z;
   const int pair = img >> 1;
   const uint8_t* rgb = (img & 1) ? pp.right[pair] : pp.left[pair];
-  // every tile pixel of this thread is loaded before the first is used, so
-  // that the loads overlap instead of each waiting for the previous one
-  constexpr int RPT = (TR + 3) / 4, CPT = (TC + 63) / 64;
-  uint32_t px[RPT][CPT][3];
+  const int t = threadIdx.y * 64 + threadIdx.x, cb = 2 * x0 - 4;  // tile column 0
+  const bool words = (W & 3) == 0 && (reinterpret_cast<uintptr_t>(rgb) & 3u) == 0 && cb >= 0 &&
+                     cb + TC <= W;
+  constexpr int NG = (TR * TG + 255) / 256;  // groups of 4 pixels per thread
+  if (words) {
+    uint32_t w[NG][3];
 #pragma unroll
-  for (int i = 0; i < RPT; ++i) {
-    const int r = threadIdx.y + 4 * i;
-    const uint8_t* row = rgb + (size_t)clampi(2 * y0 - 1 + r, 0, H - 1) * W * 3;
+    for (int k = 0; k < NG; ++k) {  // all loads first; groups past the tile repeat its last
+      const int gi = min(t + 256 * k, TR * TG - 1), r = gi / TG, c = 4 * (gi - r * TG);
+      const uint32_t* q = reinterpret_cast<const uint32_t*>(
+          rgb + ((size_t)clampi(2 * y0 - 1 + r, 0, H - 1) * W + cb + c) * 3);
+      w[k][0] = q[0];
+      w[k][1] = q[1];
+      w[k][2] = q[2];
+    }
 #pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-      // rows and columns are clamped into the image, so positions past the
-      // tile load a valid pixel too (never stored): no branch between loads
-      const int c = threadIdx.x + 64 * j;
-      const uint8_t* q = row + (size_t)clampi(2 * x0 - 1 + c, 0, W - 1) * 3;
-      px[i][j][0] = q[0];
-      px[i][j][1] = q[1];
-      px[i][j][2] = q[2];
+    for (int k = 0; k < NG; ++k) {  // no branch, so no load is sunk next to its use
+      const int gi = t + 256 * k;
+      const int r = gi < TR * TG ? gi / TG : TR, c = gi < TR * TG ? 4 * (gi - r * TG) : 0;
+      // pixel i's bytes start at byte 3i of the 12
+      const uint32_t p0 = w[k][0], p1 = __builtin_amdgcn_alignbyte(w[k][1], w[k][0], 3),
+                     p2 = __builtin_amdgcn_alignbyte(w[k][2], w[k][1], 2),
+                     p3 = __builtin_amdgcn_alignbyte(w[k][2], w[k][2], 1);
+      const uint32_t g0 = __builtin_amdgcn_udot4(p0 & 0xffffffu, kGrayW, 128u, false) >> 8;
+      const uint32_t g1 = __builtin_amdgcn_udot4(p1 & 0xffffffu, kGrayW, 128u, false) >> 8;
+      const uint32_t g2 = __builtin_amdgcn_udot4(p2 & 0xffffffu, kGrayW, 128u, false) >> 8;
+      const uint32_t g3 = __builtin_amdgcn_udot4(p3 & 0xffffffu, kGrayW, 128u, false) >> 8;
+      *reinterpret_cast<uint32_t*>(&g[r][c]) = g0 | g1 << 8 | g2 << 16 | g3 << 24;
+    }
+  } else {
+    constexpr int NP = (TR * TC + 255) / 256;  // pixels per thread
+    uint32_t px[NP][3];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {  // all loads first, clamped into the image
+      const int pi = min(t + 256 * k, TR * TC - 1), r = pi / TC, c = pi - r * TC;
+      const uint8_t* q = rgb + ((size_t)clampi(2 * y0 - 1 + r, 0, H - 1) * W +
+                                clampi(cb + c, 0, W - 1)) * 3;
+      px[k][0] = q[0];
+      px[k][1] = q[1];
+      px[k][2] = q[2];
+    }
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+      const int pi = t + 256 * k;
+      const int r = pi < TR * TC ? pi / TC : TR, c = pi < TR * TC ? pi - r * TC : 0;
+      g[r][c] = (uint8_t)((77 * px[k][0] + 150 * px[k][1] + 29 * px[k][2] + 128) >> 8);
     }
   }
-#pragma unroll
-  for (int i = 0; i < RPT; ++i)
-#pragma unroll
-    for (int j = 0; j < CPT; ++j) {
-      const int r = threadIdx.y + 4 * i, c = threadIdx.x + 64 * j;
-      if (r < TR && c < TC)
-        g[r][c] = (uint8_t)((77 * px[i][j][0] + 150 * px[i][j][1] + 29 * px[i][j][2] + 128) >> 8);
-    }
   __syncthreads();
   const int lx = threadIdx.x, x = x0 + lx;
   if (x >= X) return;
@@ -89,7 +115,7 @@ __global__ void __launch_bounds__(256) k_prep(PairPtrs pp, int W, int H, int X, 
 #pragma unroll
     for (int j = 0; j < 3; ++j)
 #pragma unroll
-      for (int i = 0; i < 3; ++i) s += g[2 * ly + j][2 * lx + i];
+      for (int i = 0; i < 3; ++i) s += g[2 * ly + j][2 * lx + 3 + i];
     half[(size_t)img * X * Y + (size_t)y * X + x] = (uint8_t)((s + 4) / 9);
   }
 }
