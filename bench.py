@@ -69,10 +69,27 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_match_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2212_00488_amd", "csrc", "kernels.hip.h")
 
 
+# The parts of the sources that decide k_match's memory traffic: the shared
+# constants and helpers at the top of the kernel header, the k_match section
+# (up to k_wta), and the host code that picks its launch geometry.
+TRAFFIC_SOURCE_PARTS = (
+    ("kernels.hip.h", None, "// ---------------------------------------------------------------- k_prep"),
+    ("kernels.hip.h", "// ---------------------------------------------------------------- k_match",
+     "// ----------------------------------------------------------------- k_wta"),
+    ("stereo.hip", "double match_makespan(", "// The d-chunk size stereo_autotune chose"),
+)
+
+
 def kernel_source_hash() -> str:
+    """sha256 (first 16 hex digits) of the source parts in TRAFFIC_SOURCE_PARTS."""
     import hashlib
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for name, start, end in TRAFFIC_SOURCE_PARTS:
+        with open(os.path.join(os.path.dirname(KERNEL_SRC), name)) as f:
+            text = f.read()
+        i = text.index(start) if start else 0
+        h.update(text[i:text.index(end, i)].encode())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic():
