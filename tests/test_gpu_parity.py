@@ -145,6 +145,28 @@ def test_parameter_variants(sm, ctx, kw):
     full_parity(sm, ctx, pair.left, pair.right, 30, keep_params(sm, **kw), label=str(kw))
 
 
+@pytest.mark.parametrize("W,H,dmax,full", [
+    (8192, 40, 512, False),   # widest half-res row (4096 columns, 64 strips) and largest D (256)
+    (40, 8192, 32, False),    # tallest: 4096 half-res rows in eight or more row bands
+    (4096, 16, 64, True),     # widest full-resolution row
+])
+def test_maximum_sides(sm, ctx, W, H, dmax, full):
+    """The largest sides the library accepts (STEREO_MAX_SIDE, or half of it
+    at full resolution) and the largest Dmax, bit-exact against the oracle."""
+    pair = make_pair(W, H, dmax, segments=6, seed=14)
+    flags = sm.F_KEEP_INTERMEDIATES | (sm.F_FULL_RES if full else 0)
+    p = sm.default_params(flags=flags, arm_x=41 if full else 21, arm_y=61 if full else 31)
+    full_parity(sm, ctx, pair.left, pair.right, dmax, p, label=f"max {W}x{H}")
+
+
+def test_largest_arms(sm, ctx):
+    """Both arms at their cap of 127 (three 128-column sub-passes of the row
+    pass; cost scale small enough for the 2^24 window-sum bound)."""
+    pair = make_pair(600, 600, 30, segments=4, seed=15)
+    p = keep_params(sm, arm_x=127, arm_y=127, cost_scale=128)
+    full_parity(sm, ctx, pair.left, pair.right, 30, p, label="arms 127")
+
+
 def test_paper_sized_workload_bit_exact(sm, ctx):
     """1436x992, Dmax 145 (718x496, D = 73 at half resolution), the shape the
     paper times; the launch configuration the benchmark uses."""
