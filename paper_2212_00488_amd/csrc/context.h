@@ -18,6 +18,10 @@ void free_soft_plans(std::vector<SoftPlan*>& plans);
 }  // namespace stereo_host
 
 namespace stereo_host {
+// d-chunk size (disparities) for groups x D of work over band rows of height
+// rows, from the model of the per-XCD dispatch queues (stereo.hip).
+int best_chunk_size(int groups, int D, int rows, int num_cu);
+
 // A launch geometry chosen by stereo_autotune for one shape and parameter set.
 struct Tuned {
   int W, H, Dmax, npair;

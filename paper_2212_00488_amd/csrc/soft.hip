@@ -22,7 +22,8 @@ constexpr size_t kSlabBudget = size_t(512) << 20;  // dL/dCA (then t) + dL/dCA_x
 struct SoftPlan {
   int n = 0, W = 0, H = 0, Dmax = 0, X = 0, Y = 0, D = 0;
   stereo_soft_params p{};
-  int ns = 1, kmax = 8, nstrips = 0, nbands = 0, nchunk = 0;
+  int ns = 1, kmax = 8, nstrips = 0, nbands = 0, rows = 0;
+  int csize = 1, nchunk = 0;   // k_soft_agg d-chunk size and forward chunk count
   int XS = 0, pads = 0, XA = 0;
   int fxk = 18;        // fixed-point bits of the costs
   int nds = 1;         // disparities per backward slab
@@ -84,22 +85,6 @@ int soft_checks(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_soft_
   return 0;
 }
 
-// Chunks of the d range so that groups x chunks workgroups (groups padded to
-// a multiple of the XCD count) fill whole rounds of CUs well.
-int fill_chunks(int groups, int num_cu, int D) {
-  const int ng = ((groups + kXcds - 1) / kXcds) * kXcds;
-  const int c0 = std::max(1, (num_cu + ng - 1) / ng);
-  int best = std::min(c0, D);
-  double best_e = 0.0;
-  for (int c = c0; c <= std::min(D, 4 * c0); ++c) {
-    const long w = (long)ng * c, rounds = (w + num_cu - 1) / num_cu;
-    const double e = (double)w / ((double)rounds * num_cu);
-    if (e >= 0.9) return c;
-    if (e > best_e) { best_e = e; best = c; }
-  }
-  return std::max(1, best);
-}
-
 int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_soft_params& p,
                    SoftPlan** out) {
   SoftPlan* pl = new SoftPlan();
@@ -126,6 +111,7 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
   }
   pl->nbands = nb;
   pl->kmax = km;
+  pl->rows = nb == 1 ? Y : std::min(Y, (Y + nb - 1) / nb + 2 * p.arm_y);
   pl->nstrips = (X + kTX - 1) / kTX;
   pl->XA = pl->nstrips * kTX;
   // row loads reach x0 - hx - d .. x0 - hx + 127 for every strip x0
@@ -133,7 +119,8 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
   pl->XS = pl->pads + pl->XA + 128 * pl->ns + 2;
   pl->XS = (pl->XS + 1) & ~1;
   const int groups = pl->nstrips * pl->nbands * n;
-  pl->nchunk = fill_chunks(groups, c->num_cu, D);
+  pl->csize = best_chunk_size(groups, D, pl->rows, c->num_cu);
+  pl->nchunk = (D + pl->csize - 1) / pl->csize;
   const size_t npix = (size_t)X * Y;
   pl->nds = p.slab > 0 ? std::min(p.slab, D)
                        : (int)std::max<size_t>(1, std::min<size_t>(D, kSlabBudget / (2 * n * npix * 4)));
@@ -229,13 +216,15 @@ void soft_features(const SoftPlan& pl, const float* left, const float* right, hi
                      pl.XA, pl.inv_size);
 }
 
-SoftArgs soft_args(const SoftPlan& pl, const float* lambdas, int dlo, int dhi, int nchunk) {
+SoftArgs soft_args(const SoftPlan& pl, const float* lambdas, int dlo, int dhi, int csize) {
   SoftArgs a{};
   a.sp = pl.sp; a.arms = pl.arms; a.lam = lambdas; a.inv_size = pl.inv_size;
   a.part = pl.part; a.pc = pl.pc; a.gca = pl.gca;
   a.X = pl.X; a.Y = pl.Y; a.XS = pl.XS; a.pads = pl.pads; a.XA = pl.XA;
   a.arm_x = pl.p.arm_x; a.arm_y = pl.p.arm_y;
-  a.nbands = pl.nbands; a.nchunk = nchunk; a.dlo = dlo; a.dhi = dhi;
+  a.nbands = pl.nbands; a.dlo = dlo; a.dhi = dhi;
+  a.csize = std::max(1, std::min(csize, dhi - dlo));
+  a.nchunk = (dhi - dlo + a.csize - 1) / a.csize;
   a.nstrips = pl.nstrips; a.ngroups = pl.nstrips * pl.nbands * pl.n; a.npair = pl.n;
   a.fx = std::ldexp(1.0f, pl.fxk);
   a.zc = (float)(std::ldexp(1.0, -pl.fxk) * 1.4426950408889634 / pl.p.tau);
@@ -334,7 +323,7 @@ int stereo_soft_forward(stereo_ctx* c, const float* left, const float* right, in
   int rc = soft_prologue(c, n, W, H, Dmax, params, &pl);
   if (rc) return rc;
   soft_features(*pl, left, right, stream);
-  launch_soft_agg<false>(*pl, soft_args(*pl, lambdas, 0, pl->D, pl->nchunk), stream);
+  launch_soft_agg<false>(*pl, soft_args(*pl, lambdas, 0, pl->D, pl->csize), stream);
   const int npix = pl->X * pl->Y;
   hipLaunchKernelGGL(k_soft_merge, dim3((npix + 255) / 256, pl->n), dim3(256), 0, stream, pl->part,
                      pl->nchunk, npix, d_hat, lse2);
@@ -364,8 +353,8 @@ int stereo_soft_backward(stereo_ctx* c, const float* left, const float* right, i
   size_t lam_off = 0;
   for (int dlo = 0; dlo < pl->D; dlo += pl->nds) {
     const int dhi = std::min(pl->D, dlo + pl->nds), nds = dhi - dlo;
-    const int nch = std::min(nds, fill_chunks(groups, c->num_cu, nds));
-    launch_soft_agg<true>(*pl, soft_args(*pl, lambdas, dlo, dhi, nch), stream);
+    const int cs = best_chunk_size(groups, nds, pl->rows, c->num_cu);
+    launch_soft_agg<true>(*pl, soft_args(*pl, lambdas, dlo, dhi, cs), stream);
     hipLaunchKernelGGL(k_soft_tcol, dim3((X + 63) / 64, (nds + 3) / 4, pl->n), dim3(64, 4),
                        4 * pl->ring * 64 * sizeof(float), stream, pl->gca, pl->arms, X, Y, pl->XA,
                        pl->p.arm_y, pl->ring, pl->n, nds, pl->gcax);

@@ -131,7 +131,8 @@ struct SoftArgs {
   const float4* pc;         // [n][Y][X] {w, log2 sum e, d_hat, A}  (GCA)
   float* gca;               // [nds][n][Y][X] dL/dCA           (GCA)
   int X, Y, XS, pads, XA, arm_x, arm_y;
-  int nbands, nchunk, dlo, dhi, nstrips, ngroups, npair;
+  int nbands, dlo, dhi, nstrips, ngroups, npair;
+  int csize, nchunk;        // d-chunk size; chunks = ceil((dhi - dlo) / csize), the last the remainder
   float fx;                 // fixed-point scale 2^k of the costs
   float zc;                 // 2^-k log2(e) / tau: CA_int * inv_size * zc = mean / tau in log2 units
   uint32_t sp_bytes, arms_bytes;
@@ -178,7 +179,8 @@ __global__ void __launch_bounds__(kThreads) k_soft_agg(SoftArgs a) {
   const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
   const int X = a.X, Y = a.Y;
   const int wg = blockIdx.x, xcd = wg & (kXcds - 1), j = wg / kXcds;
-  const int local = j / a.nchunk, chunk = j - local * a.nchunk;
+  int local, chunk;
+  chunk_at(j, (a.ngroups + kXcds - 1) / kXcds, (a.dhi - a.dlo) / a.csize, a.nchunk, local, chunk);
   int group = local * kXcds + xcd;
   if (group >= a.ngroups) return;
   const int strip = group % a.nstrips;
@@ -190,8 +192,7 @@ __global__ void __launch_bounds__(kThreads) k_soft_agg(SoftArgs a) {
   const int y0 = band * ob, y1 = min(Y, y0 + ob);
   const int ya = max(0, y0 - a.arm_y), yb = min(Y, y1 + a.arm_y);
   const int nb = yb - ya, o0 = y0 - ya, o1 = y1 - ya;
-  const int span = a.dhi - a.dlo;
-  const int d0 = a.dlo + (chunk * span) / a.nchunk, d1 = a.dlo + ((chunk + 1) * span) / a.nchunk;
+  const int d0 = a.dlo + chunk * a.csize, d1 = min(a.dhi, d0 + a.csize);
   const int hx = (a.arm_x + 2) & ~1;
   const __amdgpu_buffer_rsrc_t rs = buffer_rsrc(a.sp, a.sp_bytes);
   const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(a.arms, a.arms_bytes);
@@ -328,10 +329,17 @@ __global__ void __launch_bounds__(256) k_soft_merge(const float2* __restrict__ p
   if (i >= npix) return;
   const float2* p = part + (size_t)pair * nchunk * npix + i;
   float s = 0.f, sd = 0.f;
-  for (int c = 0; c < nchunk; ++c) {
-    const float2 v = p[(size_t)c * npix];
-    s += v.x;
-    sd += v.y;
+  // loads in groups of 8 in flight, sums in chunk order
+  for (int c0 = 0; c0 < nchunk; c0 += 8) {
+    float2 v[8];
+#pragma unroll
+    for (int g = 0; g < 8; ++g) v[g] = p[(size_t)min(c0 + g, nchunk - 1) * npix];
+#pragma unroll
+    for (int g = 0; g < 8; ++g)
+      if (c0 + g < nchunk) {
+        s += v[g].x;
+        sd += v[g].y;
+      }
   }
   dhat[(size_t)pair * npix + i] = sd / s;
   lse2[(size_t)pair * npix + i] = __log2f(s);
