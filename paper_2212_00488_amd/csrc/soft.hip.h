@@ -44,7 +44,7 @@ namespace stereo_dev {
 namespace {
 
 constexpr int kSoftBR = 16;  // output rows per k_soft_tr workgroup
-constexpr int kTrBatch = 8;  // source rows per batch of loads in k_soft_tr
+constexpr int kTcolBatch = 24;  // source rows per batch of loads in k_soft_tcol
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
@@ -373,7 +373,7 @@ __global__ void __launch_bounds__(256) k_soft_bprep(const float* __restrict__ in
 // the array lives in an LDS ring of `ring` >= 2 arm_y + 2 rows per column:
 // after source y, row y - arm_y can receive nothing more, is added to the
 // running prefix, written out and its slot cleared.  Each lane owns its
-// column's ring, so the updates need no atomics.  Loads of kTrBatch rows
+// column's ring, so the updates need no atomics.  Loads of kTcolBatch rows
 // are issued together, the next batch's before this one's updates.
 // grid: (ceil(X/64), ceil(nds/4), n), block (64, 4) = one disparity per
 // wave; dynamic LDS 4 * ring * 64 floats.
@@ -400,11 +400,11 @@ __global__ void __launch_bounds__(256) k_soft_tcol(const float* __restrict__ gca
     *slot = 0.f;
     if (xv) out[(size_t)f * X] = carry;
   };
-  float gv[2][kTrBatch];
-  uint32_t av[2][kTrBatch];
+  float gv[2][kTcolBatch];
+  uint32_t av[2][kTcolBatch];
   auto fetch = [&](int y, int buf) {
 #pragma unroll
-    for (int i = 0; i < kTrBatch; ++i) {
+    for (int i = 0; i < kTcolBatch; ++i) {
       const int yy = min(y + i, Y - 1);
       gv[buf][i] = xv ? g[(size_t)yy * X] : 0.f;
       av[buf][i] = xv ? am[(size_t)yy * XA] : 0u;
@@ -412,7 +412,7 @@ __global__ void __launch_bounds__(256) k_soft_tcol(const float* __restrict__ gca
   };
   auto scatter = [&](int y, int buf) {
 #pragma unroll
-    for (int i = 0; i < kTrBatch; ++i) {
+    for (int i = 0; i < kTcolBatch; ++i) {
       const int yy = y + i;
       if (yy >= Y) break;
       const float v = gv[buf][i];
@@ -426,12 +426,12 @@ __global__ void __launch_bounds__(256) k_soft_tcol(const float* __restrict__ gca
     }
   };
   fetch(0, 0);
-  for (int y = 0; y < Y; y += 2 * kTrBatch) {
-    if (y + kTrBatch < Y) fetch(y + kTrBatch, 1);
+  for (int y = 0; y < Y; y += 2 * kTcolBatch) {
+    if (y + kTcolBatch < Y) fetch(y + kTcolBatch, 1);
     scatter(y, 0);
-    if (y + kTrBatch >= Y) break;
-    if (y + 2 * kTrBatch < Y) fetch(y + 2 * kTrBatch, 0);
-    scatter(y + kTrBatch, 1);
+    if (y + kTcolBatch >= Y) break;
+    if (y + 2 * kTcolBatch < Y) fetch(y + 2 * kTcolBatch, 0);
+    scatter(y + kTcolBatch, 1);
   }
   for (int f = max(0, Y - arm_y); f < Y; ++f) finalize(f);
 }
