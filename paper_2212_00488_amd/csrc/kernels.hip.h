@@ -401,9 +401,12 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
     key[k] = 0xffffffffu;
-    uint32_t mn = 0u;
     const int r = o0 + wave + k * kWaves;
-    if (x < X && r < o1) mn = a.arms[((size_t)img_b * Y + ya + r) * a.XA + x] >> 16;
+    // no branch around the load (a branch made every load wait for the one
+    // before): rows past the band read its last row and are masked by a
+    // wave-uniform select; columns past X read the plane's zero padding
+    const uint32_t v = a.arms[((size_t)img_b * Y + ya + min(r, o1 - 1)) * a.XA + x] >> 16;
+    const uint32_t mn = r < o1 ? v : 0u;
     if (k & 1) marm[k / 2] |= mn << 16;
     else marm[k / 2] = mn;
   }

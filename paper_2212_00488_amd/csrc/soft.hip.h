@@ -213,16 +213,20 @@ __global__ void __launch_bounds__(kThreads) k_soft_agg(SoftArgs a) {
   float se[GCA ? 1 : KMAX], sde[GCA ? 1 : KMAX], isz[GCA ? 1 : KMAX];
 #pragma unroll
   for (int k = 0; k < KMAX; ++k) {
-    uint32_t mn = 0u;
     const int r = o0 + wave + k * kWaves;
     const bool in = x < X && r < o1;
-    if (in) mn = a.arms[((size_t)img_l * Y + ya + r) * a.XA + x] >> 16;
+    // no branch around the load (rows past the band read its last row and are
+    // masked by a wave-uniform select; columns past X read the zero padding)
+    const uint32_t v = a.arms[((size_t)img_l * Y + ya + min(r, o1 - 1)) * a.XA + x] >> 16;
+    const uint32_t mn = r < o1 ? v : 0u;
     if (k & 1) marm[k / 2] |= mn << 16;
     else marm[k / 2] = mn;
     if constexpr (!GCA) {
       se[k] = 0.f;
       sde[k] = 0.f;
-      isz[k] = in ? a.inv_size[((size_t)pair * Y + ya + r) * X + x] * a.zc : 0.f;
+      // unconditional load at a clamped pixel, then a select (as above)
+      const float iv = a.inv_size[((size_t)pair * Y + ya + min(r, o1 - 1)) * X + min(x, X - 1)];
+      isz[k] = in ? iv * a.zc : 0.f;
     }
   }
   const int fin_base = (o0 + wave + 1) * 64 + c;
