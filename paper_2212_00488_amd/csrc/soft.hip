@@ -212,8 +212,8 @@ void soft_features(const SoftPlan& pl, const float* left, const float* right, hi
                      pl.p.arm_x, pl.p.arm_y, X, 0, pl.XA, pl.pk, pl.arms);
   hipLaunchKernelGGL(k_soft_pack, dim3((X + 255) / 256, Y, n2), dim3(256), 0, s, pl.half_f, pl.pk,
                      X, Y, pl.XS, pl.pads, pl.sp);
-  hipLaunchKernelGGL(k_soft_size, dim3((X + 255) / 256, Y, pl.n), dim3(256), 0, s, pl.arms, X, Y,
-                     pl.XA, pl.inv_size);
+  hipLaunchKernelGGL(k_soft_size, dim3((X + 63) / 64, (Y + kSizeRows - 1) / kSizeRows, pl.n),
+                     dim3(64, kSizeRows), 0, s, pl.arms, X, Y, pl.XA, pl.p.arm_y, pl.inv_size);
 }
 
 SoftArgs soft_args(const SoftPlan& pl, const float* lambdas, int dlo, int dhi, int csize) {

@@ -104,21 +104,36 @@ __global__ void __launch_bounds__(256) k_soft_pack(const float* __restrict__ hal
 // ----------------------------------------------------------- k_soft_size
 // 1 / |S(x,y)| for the left image of each pair: |S| = sum over s in
 // [-M, N] of (m + n + 1) at (x, y + s) (Eq. 7-8 applied to a unit cost).
-// grid: (ceil(X/256), Y, n), block 256.
-__global__ void __launch_bounds__(256) k_soft_size(const uint32_t* __restrict__ arms, int X,
-                                                   int Y, int XA, float* __restrict__ inv_size) {
-  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, pair = blockIdx.z;
-  if (x >= X) return;
+// One workgroup = 64 columns x kSizeRows rows: the row supports m + n + 1
+// (at most 63 with arm_x <= 31) of the rows its windows reach are staged in
+// LDS as bytes, all loads issued together (rows clamped into the image; a
+// window never reaches a clamped row), and each pixel sums its window there.
+// grid: (ceil(X/64), ceil(Y/kSizeRows), n), block (64, kSizeRows).
+constexpr int kSizeRows = 16, kSizeMaxArm = 63;
+constexpr int kSizeLoads = (kSizeRows + 2 * kSizeMaxArm + kSizeRows - 1) / kSizeRows;
+
+__global__ void __launch_bounds__(64 * kSizeRows) k_soft_size(const uint32_t* __restrict__ arms,
+                                                             int X, int Y, int XA, int arm_y,
+                                                             float* __restrict__ inv_size) {
+  __shared__ uint8_t h[kSizeLoads * kSizeRows][64];
+  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kSizeRows, pair = blockIdx.z;
+  const int lx = threadIdx.x, ly = threadIdx.y, x = x0 + lx;  // x < XA: zero padding past X
   const uint32_t* a = arms + (size_t)(2 * pair) * Y * XA;
+  uint32_t v[kSizeLoads];
+#pragma unroll
+  for (int k = 0; k < kSizeLoads; ++k)
+    v[k] = a[(size_t)clampi(y0 - arm_y + ly + kSizeRows * k, 0, Y - 1) * XA + x];
+#pragma unroll
+  for (int k = 0; k < kSizeLoads; ++k)
+    h[ly + kSizeRows * k][lx] = (uint8_t)((v[k] & 255u) + ((v[k] >> 8) & 255u) + 1u);
+  __syncthreads();
+  const int y = y0 + ly;
+  if (x >= X || y >= Y) return;
   const uint32_t c = a[(size_t)y * XA + x];
-  const int M = (c >> 16) & 255, N = c >> 24;
-  int s = 0;
-#pragma unroll 8
-  for (int r = y - M; r <= y + N; ++r) {
-    const uint32_t v = a[(size_t)r * XA + x];
-    s += (int)(v & 255u) + (int)((v >> 8) & 255u) + 1;
-  }
-  inv_size[(size_t)pair * X * Y + (size_t)y * X + x] = 1.f / (float)s;
+  const int M = (c >> 16) & 255, N = c >> 24, t = ly + arm_y;  // tile row of y
+  int sum = 0;
+  for (int r = t - M; r <= t + N; ++r) sum += h[r][lx];
+  inv_size[(size_t)pair * X * Y + (size_t)y * X + x] = 1.f / (float)sum;
 }
 
 // ------------------------------------------------------------ k_soft_agg
@@ -594,11 +609,26 @@ __global__ void __launch_bounds__(256) k_soft_gimg(const float* __restrict__ t, 
   if (x >= X) return;
   const size_t plane = (size_t)X * Y;
   float gl = 0.f, gr = 0.f;
-  for (int j = 0; j < nds; ++j) {
-    const float* tp = t + ((size_t)j * npair + pair) * plane + (size_t)y * X;
-    gl += tp[x];
-    const int xs = x + dlo + j;
-    if (xs < X) gr -= tp[xs];
+  // disparities in groups of 8, all loads of a group in flight (unconditional,
+  // at clamped indices), then summed in order of j; a column x + d past the
+  // row end contributes nothing (subtracting +0 leaves every value unchanged)
+  for (int j0 = 0; j0 < nds; j0 += 8) {
+    float vl[8], vr[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = min(j0 + u, nds - 1);
+      const float* tp = t + ((size_t)j * npair + pair) * plane + (size_t)y * X;
+      vl[u] = tp[x];
+      vr[u] = tp[min(x + dlo + j, X - 1)];
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u;
+      if (j < nds) {
+        gl += vl[u];
+        gr -= x + dlo + j < X ? vr[u] : 0.f;
+      }
+    }
   }
   g_half[(size_t)(2 * pair) * plane + (size_t)y * X + x] += gl;
   g_half[(size_t)(2 * pair + 1) * plane + (size_t)y * X + x] += gr;
