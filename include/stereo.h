@@ -290,9 +290,10 @@ void stereo_server_default_config(stereo_server_config* cfg);
 int stereo_server_create(stereo_server** out, const stereo_server_config* cfg);
 
 /* Queues one frame.  left, right: HOST uint8 [H][W][3] (page-locked memory
- * makes the upload asynchronous); out: HOST int16 [H][W].  All three must
- * stay valid until the frame's result has been returned by
- * stereo_server_poll.  Returns STEREO_EINVAL for bad arguments or after
+ * makes the upload asynchronous); out: HOST int16 [H][W] (page-locked memory
+ * receives the map by DMA; pageable memory through pinned staging and a host
+ * copy).  All three must stay valid until the frame's result has been
+ * returned by stereo_server_poll.  Returns STEREO_EINVAL for bad arguments or after
  * destroy began. */
 int stereo_server_submit(stereo_server* srv, const uint8_t* left, const uint8_t* right, int W,
                          int H, int Dmax, int16_t* out, uint64_t tag);

@@ -35,6 +35,7 @@ struct Request {
   int W, H, Dmax;
   uint64_t tag;
   size_t volume;  // X * Y * D * 4 bytes: the admission measure
+  bool direct = false;  // out is page-locked: the map is copied into it directly
   Clock::time_point t_submit, t_admit;
 };
 
@@ -171,10 +172,17 @@ int start(stereo_server* s, int i, Request& r) {
     e = it->second;
   }
   const size_t img = (size_t)r.W * r.H * 3, omap = (size_t)r.W * r.H * 2;
+  // a page-locked output buffer takes the map by DMA; pageable memory goes
+  // through the slot's pinned staging and a host copy on completion
+  hipPointerAttribute_t at{};
+  r.direct = hipPointerGetAttributes(&at, r.out) == hipSuccess && at.type == hipMemoryTypeHost;
+  (void)hipGetLastError();  // the query fails for pageable memory; not an error here
   hipError_t he = hipMemcpyAsync(e->d_left, r.left, img, hipMemcpyHostToDevice, sl.stream);
   if (he == hipSuccess) he = hipMemcpyAsync(e->d_right, r.right, img, hipMemcpyHostToDevice, sl.stream);
   if (he == hipSuccess) he = hipGraphLaunch(e->exec, sl.stream);
-  if (he == hipSuccess) he = hipMemcpyAsync(e->h_out, e->d_out, omap, hipMemcpyDeviceToHost, sl.stream);
+  if (he == hipSuccess)
+    he = hipMemcpyAsync(r.direct ? (void*)r.out : (void*)e->h_out, e->d_out, omap,
+                        hipMemcpyDeviceToHost, sl.stream);
   if (he == hipSuccess) he = hipEventRecord(sl.done, sl.stream);
   if (he != hipSuccess) return fail(s->ctx, STEREO_EHIP, "enqueue: %s", hipGetErrorString(he));
   r.t_admit = Clock::now();
@@ -213,7 +221,7 @@ void worker_main(stereo_server* s) {
         status = STEREO_EHIP;
         std::lock_guard<std::mutex> g(s->mu);
         s->err = hipGetErrorString(q);
-      } else {
+      } else if (!sl.req.direct) {
         std::memcpy(sl.req.out, sl.ex->h_out, (size_t)sl.req.W * sl.req.H * 2);
       }
       sl.busy = false;

@@ -43,14 +43,17 @@ def make_stream(n, seed, rate):
     return kinds, which, arrivals
 
 
-def run_stream(pool, n, seed, rate, slots, budget=0):
+def run_stream(pool, n, seed, rate, slots, budget=0, pinned=False):
     frames, ref = pool
     kinds, which, arrivals = make_stream(n, seed, rate)
     srv = Server(0, slots=slots, mem_budget=budget)
     try:
         fr = [(frames[k][j].left, frames[k][j].right) for k, j in zip(kinds, which)]
         dm = [SHAPES[k][2] for k in kinds]
-        rep, outs = replay(srv, fr, arrivals, dm)
+        outs = None
+        if pinned:  # page-locked outputs take the maps by DMA, without staging
+            outs = [torch.empty(f[0].shape[:2], dtype=torch.int16).pin_memory().numpy() for f in fr]
+        rep, outs = replay(srv, fr, arrivals, dm, outs=outs)
     finally:
         srv.close()
     for i, (k, j) in enumerate(zip(kinds, which)):
@@ -94,3 +97,8 @@ def test_admission_budget_bounds_frames_in_flight(pool):
         live = [q for q in res if q["t_admit_ms"] <= t < q["t_done_ms"]]
         total = sum(volume(kinds[q["tag"]]) for q in live)
         assert total <= budget or len(live) == 1, (t, total, budget)
+
+
+def test_page_locked_outputs_match_alone(pool):
+    rep, _ = run_stream(pool, 32, seed=603, rate=None, slots=4, pinned=True)
+    assert len({r["slot"] for r in rep.results}) > 1
