@@ -261,28 +261,63 @@ __global__ void __launch_bounds__(kThreads) k_soft_agg(SoftArgs a) {
   for (int d = d0; d < d1; ++d) {
     const uint32_t vo = vb - (uint32_t)(d * 8);
     uint32_t run = 0;
-    for (int r = r0; r < r1; ++r) {
+    // rows in batches of two (their scans interleave), the loads of the next
+    // batch in flight while this one is processed; a batch running past the
+    // segment end loads its last row again and never stores it
+    struct RowIn { u32x4 L[NS], R[NS]; uint32_t am; };
+    auto load_row = [&](int r, RowIn& in) {
       const uint32_t y = (uint32_t)(ya + r);
       const uint32_t sl = (img_l * (uint32_t)Y + y) * sprow, sr = (img_r * (uint32_t)Y + y) * sprow;
-      uint32_t carry = 0;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        const u32x4 L = __builtin_amdgcn_raw_buffer_load_b128(rs, vb + s * 1024, sl, 0);
-        const u32x4 R = __builtin_amdgcn_raw_buffer_load_b128(rs, vo + s * 1024, sr, 0);
-        const int col = x0 - hx + s * 128 + 2 * lane;
-        const uint32_t c0 = cost(make_uint2(L.x, L.y), make_uint2(R.x, R.y), col, d);
-        const uint32_t c1 = cost(make_uint2(L.z, L.w), make_uint2(R.z, R.w), col + 1, d);
-        const uint32_t p = wave_scan_incl(c0 + c1) + carry;
-        if (NS > 1) carry = __builtin_amdgcn_readlane(p, 63);
-        *reinterpret_cast<u32x2*>(&s_row[wave][s * 128 + 2 * lane]) = u32x2{p - c1, p};
+        in.L[s] = __builtin_amdgcn_raw_buffer_load_b128(rs, vb + s * 1024, sl, 0);
+        in.R[s] = __builtin_amdgcn_raw_buffer_load_b128(rs, vo + s * 1024, sr, 0);
       }
-      const uint32_t am =
-          __builtin_amdgcn_raw_buffer_load_b32(ra, vx, (img_l * (uint32_t)Y + y) * armrow, 0);
-      WAVE_LDS_ORDER();
-      const int m = am & 255u, n = (am >> 8) & 255u;
-      run += s_row[wave][lane + hx + n] - s_row[wave][lane + hx - m - 1];
-      WAVE_LDS_ORDER();
-      s_plane[(r + 1) * 64 + lane] = run;
+      in.am = __builtin_amdgcn_raw_buffer_load_b32(ra, vx, (img_l * (uint32_t)Y + y) * armrow, 0);
+    };
+    auto row_of = [&](int r, int i) { return r + i < r1 ? r + i : r1 - 1; };
+    auto load_batch = [&](int r, RowIn (&in)[2]) {
+      load_row(row_of(r, 0), in[0]);
+      load_row(row_of(r, 1), in[1]);
+    };
+    auto process_batch = [&](int r, const RowIn (&in)[2]) {
+      uint32_t c1v[2][NS], pr[2][NS];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const int col = x0 - hx + s * 128 + 2 * lane;
+          const uint32_t c0 = cost(make_uint2(in[i].L[s].x, in[i].L[s].y),
+                                   make_uint2(in[i].R[s].x, in[i].R[s].y), col, d);
+          c1v[i][s] = cost(make_uint2(in[i].L[s].z, in[i].L[s].w),
+                           make_uint2(in[i].R[s].z, in[i].R[s].w), col + 1, d);
+          pr[i][s] = wave_scan_incl(c0 + c1v[i][s]);
+        }
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        if (i > 0 && r + i >= r1) break;
+        uint32_t carry = 0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+          const uint32_t p = pr[i][s] + carry;
+          if (NS > 1) carry = __builtin_amdgcn_readlane(p, 63);
+          *reinterpret_cast<u32x2*>(&s_row[wave][s * 128 + 2 * lane]) = u32x2{p - c1v[i][s], p};
+        }
+        WAVE_LDS_ORDER();
+        const int m = in[i].am & 255u, n = (in[i].am >> 8) & 255u;
+        run += s_row[wave][lane + hx + n] - s_row[wave][lane + hx - m - 1];
+        WAVE_LDS_ORDER();
+        s_plane[(r + i + 1) * 64 + lane] = run;
+      }
+    };
+    RowIn in0[2], in1[2];  // two buffer sets, used in turn
+    if (r0 < r1) load_batch(r0, in0);
+    for (int r = r0; r < r1; r += 4) {
+      if (r + 2 < r1) load_batch(r + 2, in1);
+      process_batch(r, in0);
+      if (r + 2 >= r1) break;
+      if (r + 4 < r1) load_batch(r + 4, in0);
+      process_batch(r + 2, in1);
     }
     s_seg[wave][c] = run;
     __syncthreads();
@@ -298,8 +333,21 @@ __global__ void __launch_bounds__(kThreads) k_soft_agg(SoftArgs a) {
     }
     __syncthreads();
     const float fd = (float)d;
+    // the adjoint's per-pixel constants of 4 output rows at a time, loaded
+    // together (unconditionally, at clamped pixels) before they are used
+    constexpr int QB = GCA ? 4 : 1;
+    float4 qv[QB];
 #pragma unroll
     for (int jj = 0; jj < KMAX / 2; ++jj) {
+      if constexpr (GCA) {
+        if ((2 * jj) % QB == 0) {
+#pragma unroll
+          for (int u = 0; u < QB; ++u) {
+            const int r = min(o0 + wave + (2 * jj + u) * kWaves, o1 - 1);
+            qv[u] = a.pc[((size_t)pair * Y + ya + r) * X + min(x, X - 1)];
+          }
+        }
+      }
       uint32_t mj = marm[jj];
       __asm__ volatile("" : "+v"(mj));
 #pragma unroll
@@ -314,12 +362,11 @@ __global__ void __launch_bounds__(kThreads) k_soft_agg(SoftArgs a) {
           sde[k] += fd * e;
         } else {
           const int r = o0 + wave + k * kWaves;
-          if (x < X && r < o1) {
-            const size_t pix = ((size_t)pair * Y + ya + r) * X + x;
-            const float4 q = a.pc[pix];
-            const float p = fast_exp2(-(float)ca * q.x - q.y);
-            a.gca[(size_t)(d - a.dlo) * a.npair * X * Y + pix] = q.w * p * (fd - q.z);
-          }
+          const float4 q = qv[k % QB];
+          const float p = fast_exp2(-(float)ca * q.x - q.y);
+          if (x < X && r < o1)
+            a.gca[(size_t)(d - a.dlo) * a.npair * X * Y + ((size_t)pair * Y + ya + r) * X + x] =
+                q.w * p * (fd - q.z);
         }
       }
     }
