@@ -80,15 +80,24 @@ TRAFFIC_SOURCE_PARTS = (
 )
 
 
+def _code_only(text: str) -> str:
+    """C++ text without comments and with whitespace runs collapsed."""
+    import re
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def kernel_source_hash() -> str:
-    """sha256 (first 16 hex digits) of the source parts in TRAFFIC_SOURCE_PARTS."""
+    """sha256 (first 16 hex digits) of the code (comments and layout removed)
+    of the source parts in TRAFFIC_SOURCE_PARTS."""
     import hashlib
     h = hashlib.sha256()
     for name, start, end in TRAFFIC_SOURCE_PARTS:
         with open(os.path.join(os.path.dirname(KERNEL_SRC), name)) as f:
             text = f.read()
         i = text.index(start) if start else 0
-        h.update(text[i:text.index(end, i)].encode())
+        h.update(_code_only(text[i:text.index(end, i)]).encode())
     return h.hexdigest()[:16]
 
 

@@ -306,7 +306,7 @@ struct MatchArgs {
   const uint32_t* pk;     // [2*npair][Y][XP]  padded: gray*2 | census << 16
   const uint32_t* arms;   // [2*npair][Y][XA]  zero past column X
   const uint16_t* tab;    // [7][kTabPitch]
-  uint32_t* keys;         // [npair][nchunk][2][nk]  (min CA) << 8 | argmin d
+  uint32_t* keys;         // [npair][nchunk][2][nk]  (min CA) << dbits | argmin d
   int X, Y, XP, pad, XA, nk, arm_x, arm_x_r, arm_y;
   int dbits;              // key = CA << dbits | d
   int nbands, dlo, dhi;
@@ -330,10 +330,11 @@ struct MatchArgs {
 //                CA_x = P[x+n] - P[x-m-1] (Eq. 7) goes into the LDS plane;
 //   column pass: segmented prefix down each column of the plane, in place, then
 //                CA = Q[y+N] - Q[y-M-1] (Eq. 8) for the band's output rows and
-//                key = min(key, CA << 8 | d): the smallest d wins ties (Step5).
+//                key = min(key, CA << dbits | d): the smallest d wins ties (Step5).
 // The right-based cost is evaluated as cost(R(x), L(x+d)), which is C^L(x+d)
 // of Eq. 6 term for term.  Sums wrap modulo 2^32; every difference taken is a
-// window sum below 2^24, hence exact.  KMAX (<= kKMax) bounds the output rows
+// window sum below 2^(32 - dbits) (the parameter check), hence exact and room
+// for d in the key's low dbits.  KMAX (<= kKMax) bounds the output rows
 // per thread: a band has at most 16 * KMAX output rows.
 // grid: ceil(groups / 8) * 8 * nchunk workgroups (1-D), block 1024.
 template <int NS, int KMAX, bool DBG>
