@@ -42,7 +42,7 @@ struct stereo_ctx {
   std::string err;
   stereo_host::Plan* last = nullptr;  // plan of the last call that kept its intermediates
   uint64_t tick = 0;
-  std::vector<stereo_host::Tuned> tuned;  // d-chunk counts chosen by stereo_autotune
+  std::vector<stereo_host::Tuned> tuned;  // d-chunk sizes chosen by stereo_autotune
   // scratch of the L1 loss entry points, grown on demand
   void* l1_block = nullptr;
   int l1_pairs = 0;
