@@ -13,6 +13,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "common.h"
 
 namespace stereo_dev {
@@ -150,11 +152,13 @@ __global__ void __launch_bounds__(256) k_prep(PairPtrs pp, int W, int H, int X, 
 }
 
 // ---------------------------------------------------------------- k_feat
-// Packed half-res pixel used by k_match: gray * 2 in bits 0..9 and the census
-// string in bits 16..21.  Columns outside the image hold kSentinel, whose
-// brightness difference to any pixel exceeds 255, so that the cost table
-// returns C_max there (the x - d < 0 / x + d >= X convention) without a branch.
-constexpr uint32_t kSentinel = 1022u;
+// Packed half-res pixels.  The differentiable head takes gray * 2 in bits
+// 0..9 and the census string in bits 16..21 (32 bits).  k_match takes gray in
+// bits 0..7 and the census string in bits 8..13 (16 bits), two pixels per
+// 32-bit load; that plane is stored twice, the second copy one pixel to the
+// right, so that the pair of pixels starting at any column is one aligned
+// word of one of the copies (half the bytes per row of the 32-bit form, which
+// k_match's row loads are bound by).
 constexpr int kFeatRows = 16;    // output rows per k_feat workgroup (one pixel per thread)
 constexpr int kMaxArm = 127;
 
@@ -209,12 +213,17 @@ __device__ __forceinline__ int arm_len(const uint8_t* p, int c, int delta, int c
 //   census: 6 neighbours in three rows, bit k = [neighbour < centre]
 //   arms  : contiguous pixels with |I - I(centre)| < delta, capped per side
 //           and at the image border; packed m | n<<8 | M<<16 | N<<24
+// Pixels go to pk (gray * 2 | census << 16, may be NULL) and to the two copies
+// of pk16 (gray | census << 8, may be NULL; the second copy copy16 elements
+// after the first, one pixel to the right); pitch XP, column x at pad + x.
+// Two workgroups share a CU only while a wave holds at most 80 SGPRs; the
+// waves-per-EU bound keeps the compiler under that (above it the kernel took
+// a fifth longer).
 // grid: (ceil(X/64), ceil(Y/kFeatRows), 2 * npair), block (64, kFeatRows).
-__global__ void __launch_bounds__(64 * kFeatRows) k_feat(const uint8_t* __restrict__ half, int X, int Y,
-                                               int delta, int arm_x_l, int arm_x_r, int arm_y,
-                                               int XP, int pad,
-                                               int XA, uint32_t* __restrict__ pk,
-                                               uint32_t* __restrict__ arms) {
+__global__ void __launch_bounds__(64 * kFeatRows) __attribute__((amdgpu_waves_per_eu(8)))
+k_feat(const uint8_t* __restrict__ half, int X, int Y, int delta, int arm_x_l, int arm_x_r,
+       int arm_y, int XP, int pad, int XA, uint32_t* __restrict__ pk,
+       uint32_t* __restrict__ arms, uint16_t* __restrict__ pk16, size_t copy16) {
   constexpr int TXW = 64 + 2 * (kMaxArm + kArmPad);
   __shared__ uint8_t tx[kFeatRows + 2][TXW];
   __shared__ uint8_t ty[kFeatRows + 2 * (kMaxArm + kArmPad)][64];
@@ -233,11 +242,10 @@ __global__ void __launch_bounds__(64 * kFeatRows) k_feat(const uint8_t* __restri
   for (int r = threadIdx.y; r < hy; r += kFeatRows)
     ty[r][threadIdx.x] = h[(size_t)clampi(y0 - my + r, 0, Y - 1) * X + cx];
   __syncthreads();
-  const int lx = threadIdx.x, x = x0 + lx;
-  if (x >= X) return;
-  {
-    const int ly = threadIdx.y, y = y0 + ly;
-    if (y >= Y) return;
+  const int lx = threadIdx.x, x = x0 + lx, ly = threadIdx.y, y = y0 + ly;
+  const bool inside = x < X && y < Y;
+  uint32_t p16 = 0;
+  if (inside) {
     const uint8_t* row = &tx[ly + 1][hx + lx];   // row[i] = I(x + i, y)
     const int c = row[0];
     int bits = 0;
@@ -252,18 +260,29 @@ __global__ void __launch_bounds__(64 * kFeatRows) k_feat(const uint8_t* __restri
     const int n = arm_len<1>(row, c, delta, arm_x, min(arm_x, X - 1 - x));
     const int M = arm_len<-64>(col, c, delta, arm_y, min(arm_y, y));
     const int N = arm_len<64>(col, c, delta, arm_y, min(arm_y, Y - 1 - y));
-    pk[((size_t)img * Y + y) * XP + pad + x] = (uint32_t)(2 * c) | ((uint32_t)bits << 16);
+    if (pk) pk[((size_t)img * Y + y) * XP + pad + x] = (uint32_t)(2 * c) | ((uint32_t)bits << 16);
     arms[((size_t)img * Y + y) * XA + x] =
         (uint32_t)m | ((uint32_t)n << 8) | ((uint32_t)M << 16) | ((uint32_t)N << 24);
+    p16 = (uint32_t)c | (uint32_t)bits << 8;
   }
-}
-
-// Fills the padded pk planes with kSentinel (run once when a plan is made;
-// k_feat later overwrites the image columns).
-__global__ void k_fill_u32(uint32_t* __restrict__ p, size_t n, uint32_t v) {
-  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n;
-       i += (size_t)gridDim.x * blockDim.x)
-    p[i] = v;
+  if (pk16) {
+    // pairs (x, x + 1) as aligned words: copy 0 from the even columns, copy 1
+    // (one column to the right) from the odd ones, the pixel x + 1 from the
+    // next lane (one wave is one row of the tile); the copy-1 pair across two
+    // workgroups (lane 63 here, lane 0 of the next) is written in halves
+    const uint32_t nb = (uint32_t)__shfl_down((int)p16, 1, 64);
+    if (inside) {
+      uint16_t* q = pk16 + ((size_t)img * Y + y) * XP + pad + x;
+      if ((lx & 1) == 0) {
+        *reinterpret_cast<uint32_t*>(q) = p16 | nb << 16;
+        if (lx == 0) q[copy16 + 1] = (uint16_t)p16;
+      } else if (lx != 63) {
+        *reinterpret_cast<uint32_t*>(q + copy16 + 1) = p16 | nb << 16;
+      } else {
+        q[copy16 + 1] = (uint16_t)p16;
+      }
+    }
+  }
 }
 
 // ---------------------------------------------------------------- k_match
@@ -290,12 +309,14 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const void* p, uin
                                            0x00020000);
 }
 
-// cost table [census distance h][signed brightness difference + 512]: 7 rows
-// of 1024 entries, row pitch 1026 so that equal differences in different rows
-// fall in different LDS banks; |difference| > 255 only arises against the
-// sentinel
-constexpr int kTabPitch = 1026;
-constexpr int kTab = 7 * kTabPitch;
+// cost table [h'][signed brightness difference + 256], h' = census distance
+// h (rows 0..6) or h + 7 for a match outside the other image (rows 7..13, all
+// C_max): 14 rows of 511 entries, row pitch 514 so that equal differences in
+// different rows fall in different LDS banks
+constexpr int kTabPitch = 514;
+constexpr int kTabRows = 14;
+constexpr int kTab = kTabRows * kTabPitch;
+constexpr int kOutBias = 7;       // added to h for a match outside the image
 
 // LDS rows of the k_match plane for NS sub-passes of 128 row-buffer columns.
 __host__ __device__ constexpr int plane_rows(int ns) {
@@ -303,16 +324,17 @@ __host__ __device__ constexpr int plane_rows(int ns) {
 }
 
 struct MatchArgs {
-  const uint32_t* pk;     // [2*npair][Y][XP]  padded: gray*2 | census << 16
+  const uint16_t* pk;     // [2][2*npair][Y][XP]  padded: gray | census << 8, two copies
   const uint32_t* arms;   // [2*npair][Y][XA]  zero past column X
-  const uint16_t* tab;    // [7][kTabPitch]
+  const uint16_t* tab;    // [kTabRows][kTabPitch]
   uint32_t* keys;         // [npair][nchunk][2][nk]  (min CA) << dbits | argmin d
   int X, Y, XP, pad, XA, nk, arm_x, arm_x_r, arm_y;
   int dbits;              // key = CA << dbits | d
   int nbands, dlo, dhi;
   int csize, nchunk;      // d-chunk size; chunks = ceil((dhi - dlo) / csize), the last the remainder
   int nstrips, ngroups;   // groups = strips x bands x 2 bases x pairs
-  uint32_t pk_bytes, arms_bytes;  // sizes of the pk and arms buffers
+  uint32_t pk_bytes, arms_bytes;  // sizes of the pk (both copies) and arms buffers
+  uint32_t copy_bytes;    // bytes from the first pk copy to the second
   // debug planes (pair 0, the single disparity dlo; used by the DBG variant)
   uint16_t* dbg_cost;
   uint32_t* dbg_cax;
@@ -380,7 +402,7 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(a.pk, a.pk_bytes);
   const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(a.arms, a.arms_bytes);
   const uint32_t img_b = (uint32_t)(2 * pair + base), img_o = (uint32_t)(2 * pair + (base ^ 1));
-  const uint32_t pkrow = (uint32_t)a.XP * 4u, armrow = (uint32_t)a.XA * 4u;
+  const uint32_t pkrow = (uint32_t)a.XP * 2u, armrow = (uint32_t)a.XA * 4u;
   const bool dbg = DBG && pair == 0 && base == a.dbg_base;
   (void)dbg;
 
@@ -421,37 +443,62 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   uint32_t k8 = 8u;  // shift operand of the SDWA arm extraction below
   __asm__ volatile("" : "+v"(k8));
   // byte offset of this lane's first column pair inside a padded pk row
-  const uint32_t vb = (uint32_t)(a.pad + x0 - hx + 2 * lane) * 4u;
+  const uint32_t vb = (uint32_t)(a.pad + x0 - hx + 2 * lane) * 2u;
   __syncthreads();
 
-  const char* tb = reinterpret_cast<const char*>(s_tab) + 1024;
-  // cost of one pixel pair: byte offset of entry (h, 512 + diff) is
-  // h * 2 * kTabPitch + 2 * diff + 1024, and the stored grays are doubled
-  auto cost = [&](uint32_t b, uint32_t o) -> uint32_t {
-    uint32_t hx;  // (b >> 16) ^ (o >> 16) in one instruction
-    __asm__("v_xor_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:WORD_1 "
-            "src1_sel:WORD_1" : "=v"(hx) : "v"(b), "v"(o));
-    const uint32_t h = __builtin_popcount(hx);
-    const int e = (int)h * (2 * kTabPitch) + ((int)(b & 0xffffu) - (int)(o & 0xffffu));
+  const char* tb = reinterpret_cast<const char*>(s_tab) + 512;
+  // cost of pixel J of a pair word: entry (h + bias, 256 + diff) at byte
+  // offset (h + bias) * 2 * kTabPitch + 2 * diff + 512; the census distance h
+  // is the popcount of the xor of the census bytes (one SDWA xor), and the
+  // popcount instruction adds the bias
+  auto cost = [&](uint32_t b, uint32_t o, uint32_t bias, auto J) -> uint32_t {
+    uint32_t hx;
+    if constexpr (decltype(J)::value == 0)
+      __asm__("v_xor_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_1 "
+              "src1_sel:BYTE_1" : "=v"(hx) : "v"(b), "v"(o));
+    else
+      __asm__("v_xor_b32_sdwa %0, %1, %2 dst_sel:DWORD dst_unused:UNUSED_PAD src0_sel:BYTE_3 "
+              "src1_sel:BYTE_3" : "=v"(hx) : "v"(b), "v"(o));
+    constexpr int sh = decltype(J)::value * 16;
+    const uint32_t h = __builtin_popcount(hx) + bias;
+    const int df = (int)((b >> sh) & 255u) - (int)((o >> sh) & 255u);
+    const int e = (int)h * (2 * kTabPitch) + df + df;
     return *reinterpret_cast<const uint16_t*>(tb + e);
   };
+  using J0 = std::integral_constant<int, 0>;
+  using J1 = std::integral_constant<int, 1>;
   const uint32_t vx = (uint32_t)x * 4u;
 
   for (int d = d0; d < d1; ++d) {
-    const uint32_t vo = vb + (uint32_t)(sgn * d * 4);
+    // a pair of other-image pixels starting at an odd column is an aligned
+    // word of the second copy (the parity of the column is that of d)
+    const uint32_t odd = (uint32_t)d & 1u;
+    const uint32_t vo = vb + (uint32_t)(sgn * d * 2) + 2u * odd;
+    const uint32_t ocopy = odd ? a.copy_bytes : 0u;
+    // where the match oc of a column falls outside the other image, its cost
+    // is C_max (the x - d < 0 / x + d >= X convention): the lookup takes the
+    // table rows kOutBias.., which hold C_max, by a bias on the census distance
+    uint32_t bias[NS][2];
+#pragma unroll
+    for (int s = 0; s < NS; ++s)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const int oc = x0 - hx + s * 128 + 2 * lane + j + sgn * d;
+        bias[s][j] = (unsigned)oc < (unsigned)X ? 0u : (uint32_t)kOutBias;
+      }
     // ---- row pass over this wave's rows r0..r1-1, kRowBatch rows at a time
     // (their lookups and scans interleave), the loads of the next batch in flight.
     // CA_x of a row is added to a running column sum, so the plane receives
     // the column prefix within the wave's segment of rows.
-    struct RowIn { u32x2 b[NS], o[NS]; uint32_t am; };
+    struct RowIn { uint32_t b[NS], o[NS]; uint32_t am; };
     auto load_row = [&](int r, RowIn& in) {
       const uint32_t y = (uint32_t)(ya + r);
       const uint32_t sb = (img_b * (uint32_t)Y + y) * pkrow;
-      const uint32_t so = (img_o * (uint32_t)Y + y) * pkrow;
+      const uint32_t so = (img_o * (uint32_t)Y + y) * pkrow + ocopy;
 #pragma unroll
       for (int s = 0; s < NS; ++s) {
-        in.b[s] = __builtin_amdgcn_raw_buffer_load_b64(rb, vb + s * 512, sb, 0);
-        in.o[s] = __builtin_amdgcn_raw_buffer_load_b64(rb, vo + s * 512, so, 0);
+        in.b[s] = __builtin_amdgcn_raw_buffer_load_b32(rb, vb + s * 256, sb, 0);
+        in.o[s] = __builtin_amdgcn_raw_buffer_load_b32(rb, vo + s * 256, so, 0);
       }
       in.am = __builtin_amdgcn_raw_buffer_load_b32(ra, vx, (img_b * (uint32_t)Y + y) * armrow, 0);
     };
@@ -495,8 +542,8 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
       for (int i = 0; i < kRowBatch; ++i)
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-          c0[i][s] = cost(in[i].b[s].x, in[i].o[s].x);
-          c1[i][s] = cost(in[i].b[s].y, in[i].o[s].y);
+          c0[i][s] = cost(in[i].b[s], in[i].o[s], bias[s][0], J0{});
+          c1[i][s] = cost(in[i].b[s], in[i].o[s], bias[s][1], J1{});
         }
 #pragma unroll
       for (int i = 0; i < kRowBatch; ++i)
@@ -662,7 +709,7 @@ __device__ __forceinline__ int median9(int* v) {
 constexpr int kRefMaxX = 4096;  // widest half-res (or full-res mode) row
 
 __global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp, int nk,
-                                                const uint32_t* __restrict__ pk, int XP, int pad,
+                                                const uint16_t* __restrict__ pk, int XP, int pad,
                                                 int X, int Y, int T, int fill_mode,
                                                 uint8_t* __restrict__ gcp_out,
                                                 int16_t* __restrict__ med_out,
@@ -675,7 +722,7 @@ __global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp
   const size_t plane = (size_t)X * Y;
   const int16_t* dl = disp + (size_t)(2 * pair) * nk;
   const int16_t* dr = disp + (size_t)(2 * pair + 1) * nk;
-  const uint32_t* pkr = pk + ((size_t)(2 * pair) * Y + y) * XP + pad;
+  const uint16_t* pkr = pk + ((size_t)(2 * pair) * Y + y) * XP + pad;
   const size_t rm = (size_t)max(y - 1, 0) * X, r0 = (size_t)y * X, rp = (size_t)min(y + 1, Y - 1) * X;
   // stage the rows: four columns per thread and round, all loads of a round
   // issued before its stores (clamped columns load a valid value, not stored)
@@ -697,7 +744,7 @@ __global__ void __launch_bounds__(256) k_refine(const int16_t* __restrict__ disp
       if (x < X) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) s_d[q][x] = a[i][q];
-        s_h[x] = (uint8_t)((hp[i] & 1023u) >> 1);
+        s_h[x] = (uint8_t)hp[i];
       }
     }
   }

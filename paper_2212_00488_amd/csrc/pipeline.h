@@ -25,7 +25,8 @@ struct Plan {
   // device memory, one block carved into planes
   void* block = nullptr;
   uint8_t* half = nullptr;    // [2*npair][Y][X]
-  uint32_t* pk = nullptr;     // [2*npair][Y][XP]  gray*2 | census<<16, kSentinel padding
+  uint16_t* pk = nullptr;     // [2][2*npair][Y][XP]  gray | census<<8, zero padding; the
+                              // second copy one column to the right
   uint32_t* arms = nullptr;   // [2*npair][Y][XA]  zero padding
   uint16_t* tab = nullptr;    // [7][kTabPitch]
   uint32_t* keys = nullptr;   // [npair][nchunk][2][Y][X]

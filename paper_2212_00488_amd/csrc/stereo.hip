@@ -181,9 +181,11 @@ void plan_geometry(Plan& pl, int num_cu, int forced_csize) {
   pl.nbands = nb;
   pl.nstrips = (pl.X + kTX - 1) / kTX;
   // pk padding covers every column a k_match lane loads: x0 - hx - D at the
-  // left, x0 - hx + 128 NS - 1 + D < X + 128 NS + D at the right
+  // left, x0 - hx + 128 NS - 1 + D < X + 128 NS + D at the right (one more in
+  // the shifted copy); pad and the pitch are even, so the pair of columns
+  // from an even column is an aligned 32-bit word
   pl.pad = ((128 * pl.ns + pl.D + 2) + 3) & ~3;
-  pl.XP = pl.X + 2 * pl.pad;
+  pl.XP = (pl.X + 2 * pl.pad + 63) & ~63;
   pl.XA = pl.nstrips * kTX;
   const int groups = pl.nstrips * pl.nbands * 2 * pl.npair;
   // d-chunks of csize disparities (the last one the remainder): the size
@@ -220,7 +222,7 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
   const size_t npk = (size_t)2 * npair * pl->Y * pl->XP, nar = (size_t)2 * npair * pl->Y * pl->XA;
   pl->nk = (int)((n + 63) & ~size_t(63));
   const size_t nk = pl->nk;
-  size_t bytes = al(2 * npair * n) + al(npk * 4) + al(nar * 4) + al(kTab * 2) +
+  size_t bytes = al(2 * npair * n) + al(2 * npk * 2) + al(nar * 4) + al(kTab * 2) +
                  al((size_t)npair * pl->nchunk * 2 * nk * 4) + al(2 * npair * nk * 2) +
                  al(2 * npair * nk * 4) + al(npair * n) + al(npair * n * 2) + al(npair * n * 2);
   if (c->mem_cap && c->used + bytes > c->mem_cap) {
@@ -237,7 +239,7 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
   pl->bytes = bytes;
   char* cur = static_cast<char*>(pl->block);
   pl->half = carve<uint8_t>(cur, 2 * npair * n);
-  pl->pk = carve<uint32_t>(cur, npk);
+  pl->pk = carve<uint16_t>(cur, 2 * npk);
   pl->arms = carve<uint32_t>(cur, nar);
   pl->tab = carve<uint16_t>(cur, kTab);
   pl->keys = carve<uint32_t>(cur, (size_t)npair * pl->nchunk * 2 * nk);
@@ -246,21 +248,19 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
   pl->gcp = carve<uint8_t>(cur, npair * n);
   pl->med = carve<int16_t>(cur, npair * n);
   pl->filled = carve<int16_t>(cur, npair * n);
-  // table [census distance h][512 + signed brightness difference]: differences
-  // beyond +-255 only arise against the padding sentinel and cost C_max
+  // table [h'][256 + signed brightness difference]: h' = census distance
+  // (rows 0..6), or census distance + kOutBias for a match outside the other
+  // image (rows 7..13), which costs C_max
   static uint16_t tab[kTab];
   std::memset(tab, 0, sizeof tab);
-  for (int hd = 0; hd < 7; ++hd)
-    for (int i = 0; i < 1024; ++i) {
-      const int a = i < 512 ? 512 - i : i - 512;
-      tab[hd * kTabPitch + i] = (uint16_t)(a < 256 ? pl->lut_ad[a] + pl->lut_mc[hd] : pl->cmax);
+  for (int hd = 0; hd < kTabRows; ++hd)
+    for (int i = 0; i < 511; ++i) {
+      const int a = i < 256 ? 256 - i : i - 256;
+      tab[hd * kTabPitch + i] = (uint16_t)(hd < kOutBias ? pl->lut_ad[a] + pl->lut_mc[hd] : pl->cmax);
     }
   e = hipMemcpy(pl->tab, tab, sizeof tab, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemset(pl->arms, 0, nar * 4);
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_fill_u32, dim3(1024), dim3(256), 0, nullptr, pl->pk, npk, kSentinel);
-    e = hipGetLastError();
-  }
+  if (e == hipSuccess) e = hipMemset(pl->pk, 0, 2 * npk * 2);
   if (e == hipSuccess) e = hipDeviceSynchronize();
   if (e != hipSuccess) {
     free_plan(pl);
@@ -336,7 +336,8 @@ MatchArgs match_args(const Plan& pl, int dlo, int dhi, int csize) {
   a.pk = pl.pk; a.arms = pl.arms; a.tab = pl.tab; a.keys = pl.keys;
   a.X = pl.X; a.Y = pl.Y; a.XP = pl.XP; a.pad = pl.pad; a.XA = pl.XA; a.nk = pl.nk;
   a.arm_x = pl.p.arm_x; a.arm_x_r = pl.p.arm_x_r; a.arm_y = pl.p.arm_y; a.dbits = pl.dbits;
-  a.pk_bytes = (uint32_t)((size_t)2 * pl.npair * pl.Y * pl.XP * 4);
+  a.copy_bytes = (uint32_t)((size_t)2 * pl.npair * pl.Y * pl.XP * 2);
+  a.pk_bytes = 2 * a.copy_bytes;
   a.arms_bytes = (uint32_t)((size_t)2 * pl.npair * pl.Y * pl.XA * 4);
   a.nbands = pl.nbands; a.dlo = dlo; a.dhi = dhi;
   a.csize = std::max(1, std::min(csize, dhi - dlo));
@@ -402,7 +403,8 @@ int run(stereo_ctx* c, Plan& pl, const PairPtrs& pp, int npair, bool keep, bool 
   hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + kFeatRows - 1) / kFeatRows, 2 * npair),
                      dim3(64, kFeatRows), 0,
                      s, pl.half, X, Y, pl.p.color_delta, pl.p.arm_x, pl.p.arm_x_r, pl.p.arm_y,
-                     pl.XP, pl.pad, pl.XA, pl.pk, pl.arms);
+                     pl.XP, pl.pad, pl.XA, nullptr, pl.arms, pl.pk,
+                     (size_t)2 * npair * Y * pl.XP);
   mark(2);
   launch_match(pl, match_args(pl, 0, pl.D, pl.csize), npair, s);
   mark(3);
@@ -658,15 +660,14 @@ int stereo_get_intermediate(stereo_ctx* c, int which, int d, void* dst, size_t b
     case STEREO_I_HALF_L: case STEREO_I_HALF_R: case STEREO_I_CENSUS_L: case STEREO_I_CENSUS_R: {
       if (!need(n)) break;
       const int img = (which == STEREO_I_HALF_R || which == STEREO_I_CENSUS_R) ? 1 : 0;
-      std::vector<uint32_t> tmp(n);
+      std::vector<uint16_t> tmp(n);
       HIP_TRY(c, hipStreamSynchronize(stream));
-      HIP_TRY(c, hipMemcpy2D(tmp.data(), (size_t)pl->X * 4,
-                             pl->pk + (size_t)img * pl->Y * pl->XP + pl->pad, (size_t)pl->XP * 4,
-                             (size_t)pl->X * 4, pl->Y, hipMemcpyDeviceToHost));
+      HIP_TRY(c, hipMemcpy2D(tmp.data(), (size_t)pl->X * 2,
+                             pl->pk + (size_t)img * pl->Y * pl->XP + pl->pad, (size_t)pl->XP * 2,
+                             (size_t)pl->X * 2, pl->Y, hipMemcpyDeviceToHost));
       const bool census = which == STEREO_I_CENSUS_L || which == STEREO_I_CENSUS_R;
       uint8_t* o = static_cast<uint8_t*>(dst);
-      for (size_t i = 0; i < n; ++i)
-        o[i] = census ? (uint8_t)((tmp[i] >> 16) & 63u) : (uint8_t)((tmp[i] & 1023u) >> 1);
+      for (size_t i = 0; i < n; ++i) o[i] = census ? (uint8_t)(tmp[i] >> 8) : (uint8_t)tmp[i];
       return 0;
     }
     case STEREO_I_ARMS_L: case STEREO_I_ARMS_R: {
