@@ -567,7 +567,10 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
     }
     s_seg[wave][c] = run;
     __syncthreads();
-    // ---- column pass: add the sum of the segments above to this segment
+    // ---- column pass: add the sum of the segments above to this segment.
+    // Each plane entry belongs to one thread; the add is an LDS atomic without
+    // return (ds_add_u32), one instruction per row and no read-add-write
+    // latency chain.
     uint32_t off = 0;
 #pragma unroll
     for (int s = 0; s < kWaves; ++s) {
@@ -576,7 +579,9 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
     }
     if (wave > 0) {
 #pragma unroll 8
-      for (int r = r0; r < r1; ++r) s_plane[(r + 1) * 64 + c] += off;
+      for (int r = r0; r < r1; ++r)
+        __hip_atomic_fetch_add(&s_plane[(r + 1) * 64 + c], off, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     __syncthreads();
     // ---- vertical window and WTA for this wave's output rows
