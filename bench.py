@@ -361,8 +361,13 @@ def main():
         torch.cuda.synchronize()
         return t0.elapsed_time(t1) / k
 
-    for i in range(args.warmup):
-        ctx.disparity(left, right, DMAX, out=outs[i % nstreams], stream=side[i % nstreams])
+    # warm-up: each stream's plan, then the launch stream's (stage times and
+    # latency), one after the other
+    for si, s in enumerate(side):
+        for _ in range(args.warmup):
+            ctx.disparity(left, right, DMAX, out=outs[si], stream=s)
+        torch.cuda.synchronize()
+    for _ in range(args.warmup):
         ctx.disparity(left, right, DMAX, out=out)
     torch.cuda.synchronize()
 
