@@ -223,6 +223,26 @@ def test_deterministic_and_batch_equals_single(sm, ctx):
     assert np.array_equal(o2.cpu().numpy(), single[0])
 
 
+def test_frames_in_flight_on_two_streams(sm, ctx):
+    # frames issued round-robin on two streams (each with its own plan), many in
+    # flight at once as in the throughput measurement: every map equals the
+    # one-stream map of its pair
+    say("case: 12 frames of 3 pairs (640x480, Dmax 64) on two streams")
+    pairs = [make_pair(640, 480, 64, segments=6, seed=s) for s in (70, 71, 72)]
+    lefts = [torch.from_numpy(p.left).cuda() for p in pairs]
+    rights = [torch.from_numpy(p.right).cuda() for p in pairs]
+    single = [ctx.disparity(l, r, 64).cpu().numpy() for l, r in zip(lefts, rights)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    torch.cuda.synchronize()
+    outs = []
+    for i in range(12):
+        p = (i // 2 + i) % 3
+        outs.append((p, ctx.disparity(lefts[p], rights[p], 64, stream=streams[i % 2])))
+    torch.cuda.synchronize()
+    for p, o in outs:
+        assert np.array_equal(o.cpu().numpy(), single[p])
+
+
 def test_errors_leave_context_usable(sm, ctx):
     pair = make_pair(64, 32, 16, segments=2, seed=60)
     lt = torch.from_numpy(pair.left).cuda()
