@@ -410,10 +410,12 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   if (t < 64) s_plane[t] = 0u;
 
   const int c = lane, x = x0 + lane;
-  // rows of the band in segments of an even length, one per wave (the row
-  // pass takes its rows in pairs)
-  const int seg_len = 2 * ((nb + 2 * kWaves - 1) / (2 * kWaves));
-  const int r0 = min(wave * seg_len, nb), r1 = min(r0 + seg_len, nb);
+  // rows of the band in segments of whole row pairs (the row pass takes its
+  // rows in pairs), one per wave in order, the pairs split as evenly as
+  // possible: the waves of each SIMD (wave mod 4) then share the rows evenly
+  const int nbat = (nb + 1) / 2, bq = nbat / kWaves, br = nbat % kWaves;
+  const int r0 = min(nb, 2 * (wave * bq + min(wave, br)));
+  const int r1 = min(nb, r0 + 2 * (bq + (wave < br)));
 
   // Output rows of this thread: r = o0 + wave + 16 k.  marm[k / 2] packs the
   // vertical arms (M, N) of two such rows, one byte each.  Rows outside the

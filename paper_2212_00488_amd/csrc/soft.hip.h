@@ -220,8 +220,12 @@ __global__ void __launch_bounds__(kThreads) k_soft_agg(SoftArgs a) {
   if (t < 64) s_plane[t] = 0u;
 
   const int c = lane, x = x0 + lane;
-  const int seg_len = 2 * ((nb + 2 * kWaves - 1) / (2 * kWaves));
-  const int r0 = min(wave * seg_len, nb), r1 = min(r0 + seg_len, nb);
+  // rows of the band in segments of whole row pairs (the row pass takes its
+  // rows in pairs), one per wave in order, the pairs split as evenly as
+  // possible: the waves of each SIMD (wave mod 4) then share the rows evenly
+  const int nbat = (nb + 1) / 2, bq = nbat / kWaves, br = nbat % kWaves;
+  const int r0 = min(nb, 2 * (wave * bq + min(wave, br)));
+  const int r1 = min(nb, r0 + 2 * (bq + (wave < br)));
 
   static_assert(KMAX % 2 == 0, "KMAX must be even");
   uint32_t marm[KMAX / 2];
