@@ -7,6 +7,7 @@
 #include <cstdint>
 #include <cstdio>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "stereo.h"
@@ -43,9 +44,8 @@ struct stereo_ctx {
   stereo_host::Plan* last = nullptr;  // plan of the last call that kept its intermediates
   uint64_t tick = 0;
   std::vector<stereo_host::Tuned> tuned;  // d-chunk sizes chosen by stereo_autotune
-  // scratch of the L1 loss entry points, grown on demand
-  void* l1_block = nullptr;
-  int l1_pairs = 0;
+  // scratch of the L1 loss entry points, one block per stream
+  std::vector<std::pair<hipStream_t, void*>> l1_blocks;
 };
 
 namespace stereo_host {

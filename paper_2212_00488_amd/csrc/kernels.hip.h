@@ -318,6 +318,33 @@ constexpr int kTabRows = 14;
 constexpr int kTab = kTabRows * kTabPitch;
 constexpr int kOutBias = 7;       // added to h for a match outside the image
 
+// Values the device cost table is built from: the tables of Eq. 4 (AD) and
+// Eq. 5 (census) in fixed point, computed on the host in double, and C_max.
+struct TabArgs {
+  uint16_t ad[256];
+  uint16_t mc[7];
+  uint16_t cmax;
+};
+
+// Set-up of a plan's device state, ordered on the plan's stream (no memset
+// node, so it may be captured in a graph): clears nzero words at zero (the
+// padding of the pixel and arm planes must read 0; the kernels write the
+// image part) and writes the cost table, entry (h', 256 + diff) = LUT_AD[|diff|]
+// + LUT_MC[h'] for h' < kOutBias, else C_max; the pitch's spare columns 0.
+// grid: any, block 256.
+__global__ void __launch_bounds__(256) k_plan_init(uint32_t* __restrict__ zero, size_t nzero,
+                                                   uint16_t* __restrict__ tab, TabArgs t) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nzero; i += stride)
+    zero[i] = 0u;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)kTab; i += stride) {
+    const int h = (int)i / kTabPitch, col = (int)i - h * kTabPitch;
+    const int a = col < 256 ? 256 - col : col - 256;
+    tab[i] = col >= 511 ? (uint16_t)0
+                        : (h < kOutBias ? (uint16_t)(t.ad[a] + t.mc[h]) : t.cmax);
+  }
+}
+
 // LDS rows of the k_match plane for NS sub-passes of 128 row-buffer columns.
 __host__ __device__ constexpr int plane_rows(int ns) {
   return (kLdsBytes - kTab * 2 - kWaves * 64 * 4 - kWaves * ns * 128 * 4) / 256 - 2;

@@ -42,17 +42,22 @@ struct Plan {
   uint32_t* dbg_ca = nullptr;
   uint64_t last_use = 0;
   const void* owner = nullptr;  // stream (or server slot) the plan belongs to
+  int pins = 0;                 // server graphs that launch into this plan's memory
+  bool captured = false;        // used under a caller's graph capture: kept until destroy
 };
 
 // Validates sizes and params (NULL = defaults) into *p.
 int common_checks(stereo_ctx* c, int W, int H, int Dmax, const stereo_params* params,
                   stereo_params* p);
 // The cached plan of (W, H, Dmax, p, owner) holding at least npair pairs,
-// made (and least recently used plans evicted under the memory cap) when
-// missing.  Calls with different owners never share scratch, so their work
-// may overlap on the device.
+// made (and least recently used plans evicted under the memory cap, except
+// pinned ones) when missing; a new plan's set-up is enqueued on stream s,
+// the stream its work will run on.  Calls with different owners never share
+// scratch, so their work may overlap on the device.
 int get_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int npair,
-             const void* owner, Plan** out);
+             const void* owner, hipStream_t s, Plan** out);
+// Frees one plan of the context (the caller has synchronised its work).
+void drop_plan(stereo_ctx* c, Plan* pl);
 // Enqueues the whole path for npair (<= plan's) pairs on stream s.  Makes no
 // allocation, memset or synchronisation, so it may be captured in a graph.
 int run(stereo_ctx* c, Plan& pl, const stereo_dev::PairPtrs& pp, int npair, bool keep,

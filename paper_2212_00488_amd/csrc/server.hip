@@ -85,7 +85,8 @@ double ms_since(const stereo_server* s, Clock::time_point t) {
   return std::chrono::duration<double, std::milli>(t - s->t0).count();
 }
 
-void free_exec(Exec* e) {
+// Frees an Exec and its plan (the slot's work with it has completed).
+void free_exec(stereo_ctx* c, Exec* e) {
   if (!e) return;
   if (e->exec) (void)hipGraphExecDestroy(e->exec);
   if (e->graph) (void)hipGraphDestroy(e->graph);
@@ -93,6 +94,10 @@ void free_exec(Exec* e) {
   if (e->d_right) (void)hipFree(e->d_right);
   if (e->d_out) (void)hipFree(e->d_out);
   if (e->h_out) (void)hipHostFree(e->h_out);
+  if (e->plan) {
+    if (e->graph) --e->plan->pins;
+    drop_plan(c, e->plan);
+  }
   delete e;
 }
 
@@ -109,12 +114,13 @@ int make_exec(stereo_server* s, int i, int W, int H, int Dmax, Exec** out) {
   if (he == hipSuccess) he = hipHostMalloc(reinterpret_cast<void**>(&e->h_out), omap, hipHostMallocDefault);
   if (he != hipSuccess) {
     (void)hipGetLastError();
-    free_exec(e);
+    free_exec(c, e);
     return fail(c, STEREO_ENOMEM, "server buffers for %dx%d: %s", W, H, hipGetErrorString(he));
   }
-  int rc = get_plan(c, W, H, Dmax, s->params, 1, &sl, &e->plan);
+  int rc = get_plan(c, W, H, Dmax, s->params, 1, &sl, sl.stream, &e->plan);
   if (rc) {
-    free_exec(e);
+    e->plan = nullptr;
+    free_exec(c, e);
     return rc;
   }
   stereo_dev::PairPtrs pp{};
@@ -133,9 +139,13 @@ int make_exec(stereo_server* s, int i, int W, int H, int Dmax, Exec** out) {
     he = hipGraphInstantiate(&e->exec, e->graph, nullptr, nullptr, 0);
     if (he != hipSuccess) rc = fail(c, STEREO_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(he));
   }
+  // the graph launches into the plan's memory: the plan must outlive it, so
+  // it is pinned against eviction
+  if (e->graph) ++e->plan->pins;
   if (rc) {
     (void)hipGetLastError();
-    free_exec(e);
+    (void)hipStreamSynchronize(sl.stream);  // the plan's set-up was enqueued there
+    free_exec(c, e);
     return rc;
   }
   *out = e;
@@ -166,6 +176,16 @@ int start(stereo_server* s, int i, Request& r) {
   Exec* e = nullptr;
   if (it == sl.execs.end()) {
     int rc = make_exec(s, i, r.W, r.H, r.Dmax, &e);
+    // out of device memory: free the resident state (graph, buffers, plan) of
+    // other shapes on idle slots, this one first, and try again
+    for (int k = 0; rc == STEREO_ENOMEM && k < (int)s->slots.size(); ++k) {
+      Slot& q = s->slots[(i + k) % s->slots.size()];
+      if (q.busy || q.execs.empty()) continue;
+      (void)hipStreamSynchronize(q.stream);
+      for (auto& kv : q.execs) free_exec(s->ctx, kv.second);
+      q.execs.clear();
+      rc = make_exec(s, i, r.W, r.H, r.Dmax, &e);
+    }
     if (rc) return rc;
     sl.execs[key] = e;
   } else {
@@ -367,7 +387,7 @@ void stereo_server_destroy(stereo_server* s) {
   (void)hipSetDevice(s->cfg.device);
   for (Slot& sl : s->slots) {
     if (sl.stream) (void)hipStreamSynchronize(sl.stream);
-    for (auto& kv : sl.execs) free_exec(kv.second);
+    for (auto& kv : sl.execs) free_exec(s->ctx, kv.second);
     if (sl.stream) (void)hipStreamDestroy(sl.stream);
     if (sl.done) (void)hipEventDestroy(sl.done);
   }

@@ -45,6 +45,8 @@ struct SoftPlan {
   float* g_half = nullptr;     // [2n][Y][X]
   float2* lam_part = nullptr;  // [lam_count]
   uint64_t last_use = 0;
+  hipStream_t owner = nullptr; // the stream the plan serves (plans are never shared
+                               // between streams, so calls on two streams may overlap)
 };
 
 void free_soft_plans(std::vector<SoftPlan*>& plans) {
@@ -86,7 +88,7 @@ int soft_checks(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_soft_
 }
 
 int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_soft_params& p,
-                   SoftPlan** out) {
+                   hipStream_t s, SoftPlan** out) {
   SoftPlan* pl = new SoftPlan();
   pl->n = n; pl->W = W; pl->H = H; pl->Dmax = Dmax; pl->p = p;
   pl->X = (W + 1) / 2; pl->Y = (H + 1) / 2; pl->D = (Dmax + 1) / 2;
@@ -131,6 +133,13 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
 
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t nimg = 2 * (size_t)n;
+  // k_soft_agg addresses the pixel and arm planes through 32-bit buffer
+  // offsets
+  if (nimg * Y * pl->XS * 8 >= (size_t(1) << 32) || nimg * Y * pl->XA * 4 >= (size_t(1) << 32)) {
+    delete pl;
+    return fail(c, STEREO_EINVAL, "%d pairs of %dx%d exceed the 4 GiB pixel or arm planes of the "
+                "soft head; pass fewer pairs per call", n, W, H);
+  }
   size_t bytes = al(nimg * npix * 4) + al(nimg * npix) + al(nimg * npix * 4) +
                  al(nimg * Y * pl->XA * 4) + al(nimg * Y * pl->XS * 8) + al(n * npix * 4) +
                  al((size_t)n * pl->nchunk * npix * 8) + al(n * npix * 16) +
@@ -161,13 +170,18 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
   pl->gcax = carve<float>(cur, (size_t)pl->nds * n * npix);
   pl->g_half = carve<float>(cur, nimg * npix);
   pl->lam_part = carve<float2>(cur, pl->lam_count);
-  // zero padding of the arm and pixel planes (kernels write the image part)
+  // zero padding of the arm and pixel planes (kernels write the image part),
+  // ordered on the plan's stream: no other stream is stalled
   e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_soft_tcol),
                           hipFuncAttributeMaxDynamicSharedMemorySize,
                           4 * pl->ring * 64 * (int)sizeof(float));
-  if (e == hipSuccess) e = hipMemset(pl->arms, 0, nimg * Y * pl->XA * 4);
-  if (e == hipSuccess) e = hipMemset(pl->sp, 0, nimg * Y * pl->XS * 8);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, s, reinterpret_cast<float*>(pl->arms),
+                       nimg * Y * pl->XA, 0.f);
+    hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, s, reinterpret_cast<float*>(pl->sp),
+                       nimg * Y * pl->XS * 2, 0.f);
+    e = hipGetLastError();
+  }
   if (e != hipSuccess) {
     (void)hipFree(pl->block);
     delete pl;
@@ -179,23 +193,25 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
 }
 
 int get_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_soft_params& p,
-                  SoftPlan** out) {
+                  hipStream_t s, SoftPlan** out) {
   for (SoftPlan* pl : c->soft_plans)
-    if (pl->n == n && pl->W == W && pl->H == H && pl->Dmax == Dmax && same_soft(pl->p, p)) {
+    if (pl->n == n && pl->W == W && pl->H == H && pl->Dmax == Dmax && pl->owner == s &&
+        same_soft(pl->p, p)) {
       pl->last_use = ++c->tick;
       *out = pl;
       return 0;
     }
   SoftPlan* pl = nullptr;
-  int rc = make_soft_plan(c, n, W, H, Dmax, p, &pl);
+  int rc = make_soft_plan(c, n, W, H, Dmax, p, s, &pl);
   if (rc == STEREO_ENOMEM && !c->soft_plans.empty()) {
     (void)hipDeviceSynchronize();
     for (SoftPlan* q : c->soft_plans) c->used -= q->bytes;
     free_soft_plans(c->soft_plans);
-    rc = make_soft_plan(c, n, W, H, Dmax, p, &pl);
+    rc = make_soft_plan(c, n, W, H, Dmax, p, s, &pl);
   }
   if (rc) return rc;
   pl->last_use = ++c->tick;
+  pl->owner = s;
   c->soft_plans.push_back(pl);
   *out = pl;
   return 0;
@@ -241,12 +257,12 @@ void launch_soft_agg(const SoftPlan& pl, const SoftArgs& a, hipStream_t s) {
 }
 
 int soft_prologue(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_soft_params* params,
-                  SoftPlan** pl) {
+                  hipStream_t s, SoftPlan** pl) {
   stereo_soft_params p;
   int rc = soft_checks(c, n, W, H, Dmax, params, &p);
   if (rc) return rc;
   HIP_TRY(c, hipSetDevice(c->device));
-  return get_soft_plan(c, n, W, H, Dmax, p, pl);
+  return get_soft_plan(c, n, W, H, Dmax, p, s, pl);
 }
 
 int launch_status(stereo_ctx* c) {
@@ -257,23 +273,23 @@ int launch_status(stereo_ctx* c) {
 
 constexpr int kL1Blocks = 64;  // partial-sum blocks per pair
 
-// L1 scratch of the context for n pairs: partials [n][kL1Blocks], counts [n],
-// loss [1].  Grows on demand (after a device synchronisation).
-int l1_scratch(stereo_ctx* c, int n, float2** part, float** counts, float** loss) {
-  if (c->l1_pairs < n) {
-    HIP_TRY(c, hipDeviceSynchronize());
-    if (c->l1_block) (void)hipFree(c->l1_block);
-    c->l1_block = nullptr;
-    c->l1_pairs = 0;
-    const size_t bytes = (size_t)kSoftMaxPairs * (kL1Blocks * 8 + 4) + 256;
-    hipError_t e = hipMalloc(&c->l1_block, bytes);
+// L1 scratch of the context for the stream s: partials [kSoftMaxPairs][kL1Blocks],
+// counts [kSoftMaxPairs], loss [1]; one block per stream (made on first use),
+// so losses on two streams never share partial sums.
+int l1_scratch(stereo_ctx* c, hipStream_t s, float2** part, float** counts, float** loss) {
+  void* block = nullptr;
+  for (const auto& b : c->l1_blocks)
+    if (b.first == s) block = b.second;
+  if (!block) {
+    const size_t bytes = (size_t)kSoftMaxPairs * (kL1Blocks * 8 + 4) + 1024;
+    hipError_t e = hipMalloc(&block, bytes);
     if (e != hipSuccess) {
       (void)hipGetLastError();
       return fail(c, STEREO_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
     }
-    c->l1_pairs = kSoftMaxPairs;
+    c->l1_blocks.emplace_back(s, block);
   }
-  char* cur = static_cast<char*>(c->l1_block);
+  char* cur = static_cast<char*>(block);
   *part = carve<float2>(cur, (size_t)kSoftMaxPairs * kL1Blocks);
   *counts = carve<float>(cur, kSoftMaxPairs);
   *loss = carve<float>(cur, 1);
@@ -320,7 +336,7 @@ int stereo_soft_forward(stereo_ctx* c, const float* left, const float* right, in
   c->err.clear();
   if (!left || !right || !lambdas || !d_hat || !lse2) return fail(c, STEREO_EINVAL, "null pointer");
   SoftPlan* pl = nullptr;
-  int rc = soft_prologue(c, n, W, H, Dmax, params, &pl);
+  int rc = soft_prologue(c, n, W, H, Dmax, params, stream, &pl);
   if (rc) return rc;
   soft_features(*pl, left, right, stream);
   launch_soft_agg<false>(*pl, soft_args(*pl, lambdas, 0, pl->D, pl->csize), stream);
@@ -340,7 +356,7 @@ int stereo_soft_backward(stereo_ctx* c, const float* left, const float* right, i
       !g_lambdas)
     return fail(c, STEREO_EINVAL, "null pointer");
   SoftPlan* pl = nullptr;
-  int rc = soft_prologue(c, n, W, H, Dmax, params, &pl);
+  int rc = soft_prologue(c, n, W, H, Dmax, params, stream, &pl);
   if (rc) return rc;
   const int X = pl->X, Y = pl->Y, npix = X * Y;
   soft_features(*pl, left, right, stream);
@@ -387,7 +403,7 @@ int stereo_soft_l1_loss(stereo_ctx* c, const float* d_hat, const int16_t* gt,
   if (rc) return rc;
   float2* part;
   float *counts, *scratch_loss;
-  rc = l1_scratch(c, n, &part, &counts, &scratch_loss);
+  rc = l1_scratch(c, stream, &part, &counts, &scratch_loss);
   if (rc) return rc;
   l1_reduce(n, W, H, d_hat, gt, nonocc, part, counts, loss, stream);
   return launch_status(c);
@@ -403,7 +419,7 @@ int stereo_soft_l1_grad(stereo_ctx* c, const float* d_hat, const int16_t* gt,
   if (rc) return rc;
   float2* part;
   float *counts, *scratch_loss;
-  rc = l1_scratch(c, n, &part, &counts, &scratch_loss);
+  rc = l1_scratch(c, stream, &part, &counts, &scratch_loss);
   if (rc) return rc;
   l1_reduce(n, W, H, d_hat, gt, nonocc, part, counts, scratch_loss, stream);
   const int X = (W + 1) / 2, Y = (H + 1) / 2, npix = X * Y;

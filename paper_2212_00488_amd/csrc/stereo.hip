@@ -203,28 +203,87 @@ int tuned_csize(const stereo_ctx* c, int W, int H, int Dmax, int npair, const st
   return 0;
 }
 
-int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int npair,
-              Plan** out) {
-  Plan* pl = new Plan();
-  pl->W = W; pl->H = H; pl->Dmax = Dmax; pl->npair = npair;
-  if (full_res(p)) {
-    pl->X = W; pl->Y = H; pl->D = Dmax;
-  } else {
-    pl->X = (W + 1) / 2; pl->Y = (H + 1) / 2; pl->D = (Dmax + 1) / 2;
-  }
-  pl->dbits = key_dbits(pl->D);
-  pl->p = p;
-  build_tables(p, pl->lut_ad, pl->lut_mc);
-  pl->cmax = pl->lut_ad[255] + pl->lut_mc[6];
-  plan_geometry(*pl, c->num_cu, tuned_csize(c, W, H, Dmax, npair, p));
-  const size_t n = (size_t)pl->X * pl->Y;
+// Device bytes of a plan's block and of its pixel (pk, both copies) and arm
+// planes, for the geometry already in pl.
+struct PlanBytes {
+  size_t total, pk, arms;
+};
+
+PlanBytes plan_bytes(const Plan& pl) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
-  const size_t npk = (size_t)2 * npair * pl->Y * pl->XP, nar = (size_t)2 * npair * pl->Y * pl->XA;
-  pl->nk = (int)((n + 63) & ~size_t(63));
-  const size_t nk = pl->nk;
-  size_t bytes = al(2 * npair * n) + al(2 * npk * 2) + al(nar * 4) + al(kTab * 2) +
-                 al((size_t)npair * pl->nchunk * 2 * nk * 4) + al(2 * npair * nk * 2) +
-                 al(2 * npair * nk * 4) + al(npair * n) + al(npair * n * 2) + al(npair * n * 2);
+  const size_t n = (size_t)pl.X * pl.Y, npair = pl.npair;
+  const size_t npk = (size_t)2 * npair * pl.Y * pl.XP, nar = (size_t)2 * npair * pl.Y * pl.XA;
+  const size_t nk = pl.nk;
+  PlanBytes b;
+  b.pk = 2 * npk * 2;
+  b.arms = nar * 4;
+  b.total = al(2 * npair * n) + al(b.pk) + al(b.arms) + al(kTab * 2) +
+            al((size_t)npair * pl.nchunk * 2 * nk * 4) + al(2 * npair * nk * 2) +
+            al(2 * npair * nk * 4) + al(npair * n) + al(npair * n * 2) + al(npair * n * 2);
+  return b;
+}
+
+// Shape, tables and launch geometry of a plan (host side only, no device
+// memory); rejects shapes whose pixel or arm planes the kernels' 32-bit
+// buffer offsets cannot address.
+int plan_setup(stereo_ctx* c, Plan& pl, int W, int H, int Dmax, const stereo_params& p,
+               int npair, int forced_csize) {
+  pl.W = W; pl.H = H; pl.Dmax = Dmax; pl.npair = npair;
+  if (full_res(p)) {
+    pl.X = W; pl.Y = H; pl.D = Dmax;
+  } else {
+    pl.X = (W + 1) / 2; pl.Y = (H + 1) / 2; pl.D = (Dmax + 1) / 2;
+  }
+  pl.dbits = key_dbits(pl.D);
+  pl.p = p;
+  build_tables(p, pl.lut_ad, pl.lut_mc);
+  pl.cmax = pl.lut_ad[255] + pl.lut_mc[6];
+  plan_geometry(pl, c->num_cu, forced_csize);
+  pl.nk = (int)(((size_t)pl.X * pl.Y + 63) & ~size_t(63));
+  const PlanBytes b = plan_bytes(pl);
+  if (b.pk >= (size_t(1) << 32) || b.arms >= (size_t(1) << 32))
+    return fail(c, STEREO_EINVAL, "%d pairs of %dx%d exceed the 4 GiB pixel or arm planes", npair,
+                W, H);
+  return 0;
+}
+
+// Carves the planes of pl from the device block at base and enqueues their
+// set-up on stream s: padding cleared, cost table written (k_plan_init).
+void plan_carve_and_init(Plan& pl, void* base, hipStream_t s) {
+  const size_t n = (size_t)pl.X * pl.Y, npair = pl.npair, nk = pl.nk;
+  const PlanBytes b = plan_bytes(pl);
+  char* cur = static_cast<char*>(base);
+  pl.half = carve<uint8_t>(cur, 2 * npair * n);
+  pl.pk = carve<uint16_t>(cur, b.pk / 2);
+  pl.arms = carve<uint32_t>(cur, b.arms / 4);
+  pl.tab = carve<uint16_t>(cur, kTab);
+  pl.keys = carve<uint32_t>(cur, npair * pl.nchunk * 2 * nk);
+  pl.disp = carve<int16_t>(cur, 2 * npair * nk);
+  pl.mincost = carve<uint32_t>(cur, 2 * npair * nk);
+  pl.gcp = carve<uint8_t>(cur, npair * n);
+  pl.med = carve<int16_t>(cur, npair * n);
+  pl.filled = carve<int16_t>(cur, npair * n);
+  TabArgs t{};
+  for (int i = 0; i < 256; ++i) t.ad[i] = pl.lut_ad[i];
+  for (int i = 0; i < 7; ++i) t.mc[i] = pl.lut_mc[i];
+  t.cmax = (uint16_t)pl.cmax;
+  // pk and arms are adjacent in the block: one cleared range covers both
+  const size_t nzero = (size_t)(reinterpret_cast<char*>(pl.arms) + b.arms -
+                                reinterpret_cast<char*>(pl.pk)) / 4;
+  const unsigned blocks = (unsigned)std::min<size_t>(2048, (nzero + 1023) / 1024 + 1);
+  hipLaunchKernelGGL(k_plan_init, dim3(blocks), dim3(256), 0, s,
+                     reinterpret_cast<uint32_t*>(pl.pk), nzero, pl.tab, t);
+}
+
+int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int npair,
+              hipStream_t s, Plan** out) {
+  Plan* pl = new Plan();
+  int rc = plan_setup(c, *pl, W, H, Dmax, p, npair, tuned_csize(c, W, H, Dmax, npair, p));
+  if (rc) {
+    delete pl;
+    return rc;
+  }
+  const size_t bytes = plan_bytes(*pl).total;
   if (c->mem_cap && c->used + bytes > c->mem_cap) {
     delete pl;
     return fail(c, STEREO_ENOMEM, "plan needs %zu bytes, cap %zu, in use %zu", bytes, c->mem_cap,
@@ -237,31 +296,10 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
     return fail(c, STEREO_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
   }
   pl->bytes = bytes;
-  char* cur = static_cast<char*>(pl->block);
-  pl->half = carve<uint8_t>(cur, 2 * npair * n);
-  pl->pk = carve<uint16_t>(cur, 2 * npk);
-  pl->arms = carve<uint32_t>(cur, nar);
-  pl->tab = carve<uint16_t>(cur, kTab);
-  pl->keys = carve<uint32_t>(cur, (size_t)npair * pl->nchunk * 2 * nk);
-  pl->disp = carve<int16_t>(cur, 2 * npair * nk);
-  pl->mincost = carve<uint32_t>(cur, 2 * npair * nk);
-  pl->gcp = carve<uint8_t>(cur, npair * n);
-  pl->med = carve<int16_t>(cur, npair * n);
-  pl->filled = carve<int16_t>(cur, npair * n);
-  // table [h'][256 + signed brightness difference]: h' = census distance
-  // (rows 0..6), or census distance + kOutBias for a match outside the other
-  // image (rows 7..13), which costs C_max
-  static uint16_t tab[kTab];
-  std::memset(tab, 0, sizeof tab);
-  for (int hd = 0; hd < kTabRows; ++hd)
-    for (int i = 0; i < 511; ++i) {
-      const int a = i < 256 ? 256 - i : i - 256;
-      tab[hd * kTabPitch + i] = (uint16_t)(hd < kOutBias ? pl->lut_ad[a] + pl->lut_mc[hd] : pl->cmax);
-    }
-  e = hipMemcpy(pl->tab, tab, sizeof tab, hipMemcpyHostToDevice);
-  if (e == hipSuccess) e = hipMemset(pl->arms, 0, nar * 4);
-  if (e == hipSuccess) e = hipMemset(pl->pk, 0, 2 * npk * 2);
-  if (e == hipSuccess) e = hipDeviceSynchronize();
+  // set-up on the stream the plan serves: later work on that stream follows
+  // it, and no other stream or slot is stalled
+  plan_carve_and_init(*pl, pl->block, s);
+  e = hipGetLastError();
   if (e != hipSuccess) {
     free_plan(pl);
     return fail(c, STEREO_EHIP, "plan initialisation: %s", hipGetErrorString(e));
@@ -272,7 +310,7 @@ int make_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int
 }
 
 int get_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int npair,
-             const void* owner, Plan** out) {
+             const void* owner, hipStream_t s, Plan** out) {
   for (Plan* pl : c->plans)
     if (pl->W == W && pl->H == H && pl->Dmax == Dmax && pl->npair >= npair && pl->owner == owner &&
         same_params(pl->p, p)) {
@@ -280,19 +318,31 @@ int get_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int 
       *out = pl;
       return 0;
     }
+  // a new plan needs an allocation, which a stream under graph capture
+  // cannot make
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return fail(c, STEREO_EINVAL,
+                "no scratch yet for %dx%d Dmax %d on this stream: make one call outside the "
+                "graph capture first (or use stereo_disparity_noalloc)", W, H, Dmax);
+  (void)hipGetLastError();
   Plan* pl = nullptr;
-  int rc = make_plan(c, W, H, Dmax, p, npair, &pl);
+  int rc = make_plan(c, W, H, Dmax, p, npair, s, &pl);
   if (rc == STEREO_ENOMEM && !c->plans.empty()) {
-    // evict least recently used plans that are not the kept one, then retry
+    // evict least recently used plans, except the one whose intermediates are
+    // kept and those a captured graph still launches into, then retry
     std::sort(c->plans.begin(), c->plans.end(),
               [](Plan* a, Plan* b) { return a->last_use < b->last_use; });
     for (size_t i = 0; i < c->plans.size() && rc == STEREO_ENOMEM;) {
-      if (c->plans[i] == c->last) { ++i; continue; }
+      if (c->plans[i] == c->last || c->plans[i]->pins > 0 || c->plans[i]->captured) {
+        ++i;
+        continue;
+      }
       (void)hipDeviceSynchronize();
       c->used -= c->plans[i]->bytes;
       free_plan(c->plans[i]);
       c->plans.erase(c->plans.begin() + i);
-      rc = make_plan(c, W, H, Dmax, p, npair, &pl);
+      rc = make_plan(c, W, H, Dmax, p, npair, s, &pl);
     }
   }
   if (rc) return rc;
@@ -303,9 +353,25 @@ int get_plan(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p, int 
   return 0;
 }
 
+void drop_plan(stereo_ctx* c, Plan* pl) {
+  for (size_t i = 0; i < c->plans.size(); ++i)
+    if (c->plans[i] == pl) {
+      if (c->last == pl) c->last = nullptr;
+      c->used -= pl->bytes;
+      free_plan(pl);
+      c->plans.erase(c->plans.begin() + i);
+      return;
+    }
+}
+
 // Frees every plan of (W, H, Dmax, p), whatever its owner (after the device
 // has finished with them), so that the next call makes it again.
 int evict_shape(stereo_ctx* c, int W, int H, int Dmax, const stereo_params& p) {
+  for (const Plan* pl : c->plans)
+    if (pl->W == W && pl->H == H && pl->Dmax == Dmax && same_params(pl->p, p) &&
+        (pl->pins > 0 || pl->captured))
+      return fail(c, STEREO_EINVAL, "a captured graph uses the scratch of %dx%d Dmax %d; tune "
+                  "before capturing", W, H, Dmax);
   HIP_TRY(c, hipDeviceSynchronize());
   for (size_t i = 0; i < c->plans.size();) {
     Plan* pl = c->plans[i];
@@ -495,7 +561,7 @@ void stereo_destroy(stereo_ctx* c) {
   for (hipEvent_t e : c->events) (void)hipEventDestroy(e);
   for (Plan* pl : c->plans) free_plan(pl);
   free_soft_plans(c->soft_plans);
-  if (c->l1_block) (void)hipFree(c->l1_block);
+  for (auto& b : c->l1_blocks) (void)hipFree(b.second);
   delete c;
 }
 
@@ -516,8 +582,14 @@ int stereo_disparity_batch(stereo_ctx* c, const uint8_t* const* left, const uint
   const bool keep = (p.flags & STEREO_F_KEEP_INTERMEDIATES) != 0;
   const int per = std::min(n, kMaxPairs);
   Plan* pl = nullptr;
-  rc = get_plan(c, W, H, Dmax, p, per, stream, &pl);
+  rc = get_plan(c, W, H, Dmax, p, per, stream, stream, &pl);
   if (rc) return rc;
+  // a graph captured from this call launches into the plan's memory later:
+  // the plan is never evicted for another (it is freed by stereo_destroy)
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(stream, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    pl->captured = true;
+  (void)hipGetLastError();
   for (int i0 = 0; i0 < n; i0 += kMaxPairs) {
     const int m = std::min(kMaxPairs, n - i0);
     PairPtrs pp{};
@@ -577,7 +649,7 @@ int stereo_autotune(stereo_ctx* c, const uint8_t* const* left, const uint8_t* co
     set_tuned(c, W, H, Dmax, m, p, cand[k]);
     rc = evict_shape(c, W, H, Dmax, p);
     Plan* pl = nullptr;
-    if (!rc) rc = get_plan(c, W, H, Dmax, p, m, stream, &pl);
+    if (!rc) rc = get_plan(c, W, H, Dmax, p, m, stream, stream, &pl);
     if (!rc) rc = run(c, *pl, pp, m, false, false, stream);  // warm
     constexpr int kReps = 5;
     if (!rc) he = hipEventRecord(e0, stream);

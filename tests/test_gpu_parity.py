@@ -174,6 +174,13 @@ def test_paper_sized_workload_bit_exact(sm, ctx):
     full_parity(sm, ctx, pair.left, pair.right, 145, label="paper")
 
 
+def test_largest_served_shape_bit_exact(sm, ctx):
+    """2872x1984, Dmax 290 (1436x992, D = 145 at half resolution: three row
+    bands, an 8-bit d field), the largest shape of the served workload."""
+    pair = make_pair(2872, 1984, 290, segments=40, textureless=0.1, seed=10030)
+    full_parity(sm, ctx, pair.left, pair.right, 290, label="served 2872x1984")
+
+
 def test_batched_workload_bit_exact(sm, ctx):
     """8 x 1920x1080, Dmax 256 in one batched launch sequence; every pair's
     output equals the oracle's."""
@@ -271,6 +278,69 @@ def test_errors_leave_context_usable(sm, ctx):
     got = ctx.disparity(lt, rt, 16)
     torch.cuda.synchronize()
     assert np.array_equal(got.cpu().numpy(), oracle.disparity(pair.left, pair.right, 16)["out"])
+
+
+def test_captured_plan_is_not_evicted(sm):
+    """Under a memory cap, a plan a captured graph launches into is kept: a
+    later call of another shape that would need its memory fails with
+    STEREO_ENOMEM instead, and the graph's replays stay correct."""
+    import re
+    a = make_pair(320, 240, 32, segments=3, seed=62)
+    b = make_pair(480, 320, 48, segments=3, seed=63)
+    la, ra = torch.from_numpy(a.left).cuda(), torch.from_numpy(a.right).cuda()
+    lb, rb = torch.from_numpy(b.left).cuda(), torch.from_numpy(b.right).cuda()
+
+    def need(left, right, dmax):  # bytes of a plan, from the cap's error text
+        c = sm.Stereo(0, mem_cap=1)
+        with pytest.raises(sm.StereoError):
+            c.disparity(left, right, dmax)
+        n = int(re.search(r"needs (\d+) bytes", c.last_error()).group(1))
+        c.close()
+        return n
+
+    na, nb = need(la, ra, 32), need(lb, rb, 48)
+    c = sm.Stereo(0, mem_cap=na + nb - 1)
+    s = torch.cuda.Stream()
+    ref = oracle.disparity(a.left, a.right, 32)["out"]
+    out = torch.empty((240, 320), dtype=torch.int16, device="cuda")
+    with torch.cuda.stream(s):
+        c.disparity(la, ra, 32, out=out, stream=s)      # the plan exists before capture
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        c.disparity(la, ra, 32, out=out, stream=s)
+    with torch.cuda.stream(s):
+        with pytest.raises(sm.StereoError) as e:
+            c.disparity(lb, rb, 48, stream=s)           # would evict the captured plan
+    assert e.value.code == -2
+    for _ in range(2):
+        out.fill_(-1)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref)
+    del g
+    c.close()
+
+
+def test_new_shape_under_capture_is_refused(sm, ctx):
+    """A first call of a shape needs an allocation, which a capturing stream
+    cannot make: the call fails cleanly and the context stays usable."""
+    p = make_pair(112, 80, 16, segments=2, seed=64)
+    lt, rt = torch.from_numpy(p.left).cuda(), torch.from_numpy(p.right).cuda()
+    s = torch.cuda.Stream()
+    g = torch.cuda.CUDAGraph()
+    err = None
+    with torch.cuda.graph(g, stream=s):
+        try:
+            ctx.disparity(lt, rt, 16, stream=s)
+        except sm.StereoError as e:
+            err = e
+    assert err is not None and err.code == -1 and "capture" in ctx.last_error()
+    del g
+    got = ctx.disparity(lt, rt, 16)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), oracle.disparity(p.left, p.right, 16)["out"])
 
 
 def test_memory_cap(sm):

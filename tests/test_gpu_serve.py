@@ -1,34 +1,37 @@
 """Serving runtime on the GPU: frames of mixed shapes submitted while others
-are in flight must come back bit-identical to the same frames computed alone
-by stereo_disparity, with slots overlapping on the device and the admission
-budget respected."""
+are in flight must come back bit-identical to the oracle's map of the same
+frame (each pool frame's oracle map is computed once), with slots
+overlapping on the device and the admission budget respected.  The pool
+holds the four shapes of the served workload (640x480 Dmax 64, 1436x992
+Dmax 145, 1920x1080 Dmax 256, 2872x1984 Dmax 290) and three smaller ones,
+one of them odd-sized."""
+
+import sys
 
 import numpy as np
 import pytest
 import torch
 
+import oracle
 from paper_2212_00488_amd import Stereo
 from paper_2212_00488_amd.serve import Server, replay
 from paper_2212_00488_amd.synth import make_pair
 
 pytestmark = pytest.mark.gpu
 
-SHAPES = [(160, 120, 16), (320, 240, 32), (641, 479, 64), (1436, 992, 145)]
+SHAPES = [(160, 120, 16), (320, 240, 32), (641, 479, 64), (640, 480, 64), (1436, 992, 145),
+          (1920, 1080, 256), (2872, 1984, 290)]
 
 
 @pytest.fixture(scope="module")
 def pool():
-    frames = {}
+    frames, ref = {}, {}
     for k, (W, H, dmax) in enumerate(SHAPES):
+        print(f"[serve pool] oracle maps of {W}x{H} Dmax={dmax}", flush=True)
         frames[k] = [make_pair(W, H, dmax, segments=6, seed=10000 + 10 * k + j) for j in range(2)]
-    ctx = Stereo(0)
-    ref = {}
-    for k, (W, H, dmax) in enumerate(SHAPES):
         for j, p in enumerate(frames[k]):
-            out = ctx.disparity(torch.from_numpy(p.left).cuda(), torch.from_numpy(p.right).cuda(),
-                                dmax)
-            ref[(k, j)] = out.cpu().numpy()
-    ctx.close()
+            ref[(k, j)] = oracle.disparity(p.left, p.right, dmax)["out"]
+    sys.stdout.flush()
     return frames, ref
 
 
@@ -89,7 +92,7 @@ def test_poisson_stream_single_slot_matches_alone(pool):
 
 
 def test_admission_budget_bounds_frames_in_flight(pool):
-    budget = volume(3) + volume(0)  # a paper-sized frame and one small frame
+    budget = volume(4) + volume(0)  # a paper-sized frame and one small frame
     rep, kinds = run_stream(pool, 40, seed=602, rate=None, slots=4, budget=budget)
     res = rep.results
     for r in res:
@@ -102,3 +105,18 @@ def test_admission_budget_bounds_frames_in_flight(pool):
 def test_page_locked_outputs_match_alone(pool):
     rep, _ = run_stream(pool, 32, seed=603, rate=None, slots=4, pinned=True)
     assert len({r["slot"] for r in rep.results}) > 1
+
+
+def test_served_maps_equal_stereo_disparity(pool):
+    """The same frames computed alone by stereo_disparity equal the oracle
+    too: alone and in the mix give one result."""
+    frames, ref = pool
+    ctx = Stereo(0)
+    try:
+        for k, (W, H, dmax) in enumerate(SHAPES):
+            p = frames[k][0]
+            out = ctx.disparity(torch.from_numpy(p.left).cuda(), torch.from_numpy(p.right).cuda(),
+                                dmax)
+            assert np.array_equal(out.cpu().numpy(), ref[(k, 0)]), SHAPES[k]
+    finally:
+        ctx.close()

@@ -53,17 +53,17 @@ def to_dev(a, dtype=None):
     return t.to(dtype) if dtype is not None else t
 
 
-def sp_from(p: osoft.SoftParams):
+def sp_from(p: osoft.SoftParams, slab=0):
     return soft_default_params(tau=p.tau, color_delta=p.color_delta, arm_x=p.arm_x,
-                               arm_y=p.arm_y)
+                               arm_y=p.arm_y, slab=slab)
 
 
-def run_gpu(ctx, L, R, G, M, dmax, p, lam=None):
+def run_gpu(ctx, L, R, G, M, dmax, p, lam=None, slab=0):
     lam = lam if lam is not None else (p.lambda_ad, p.lambda_census)
     left = to_dev(L).requires_grad_(True)
     right = to_dev(R).requires_grad_(True)
     lambdas = torch.tensor(lam, dtype=torch.float32, device=DEV, requires_grad=True)
-    d_hat = soft_disparity(ctx, left, right, lambdas, dmax, sp_from(p))
+    d_hat = soft_disparity(ctx, left, right, lambdas, dmax, sp_from(p, slab))
     loss = l1_loss(ctx, d_hat, to_dev(G.astype(np.int16)), to_dev(M.astype(np.uint8)))
     loss.backward()
     torch.cuda.synchronize()
@@ -93,14 +93,20 @@ def assert_grad_close(g, r, name, rel=1e-3):
 
 @pytest.mark.parametrize("case", [
     dict(W=64, H=48, dmax=32, n=2, seed=500),          # the FD configuration (D = 16)
+    # the same with the adjoint in slabs of 3 and of 5 disparities (6 and 4
+    # slabs, the last ones short): slab offsets and per-slab lambda partials
+    dict(W=64, H=48, dmax=32, n=2, seed=500, slab=3),
+    dict(W=64, H=48, dmax=32, n=2, seed=500, slab=5),
     dict(W=67, H=41, dmax=20, n=1, seed=510),          # odd sizes, ragged strip and band
+    dict(W=67, H=41, dmax=20, n=1, seed=510, slab=4),
     dict(W=150, H=30, dmax=40, n=3, seed=520),         # three strips
 ])
 def test_forward_loss_and_gradients_match_oracle(ctx, case):
     W, H, dmax, n, seed = case["W"], case["H"], case["dmax"], case["n"], case["seed"]
     L, R, G, M = float_pairs(n, W, H, dmax, seed, noise=0.002)
     p = osoft.SoftParams()
-    d_hat, loss, gl, gr, glam = run_gpu(ctx, L, R, G, M, dmax, p)
+    print(f"[soft] {W}x{H} Dmax={dmax} n={n} slab={case.get('slab', 0)}", flush=True)
+    d_hat, loss, gl, gr, glam = run_gpu(ctx, L, R, G, M, dmax, p, slab=case.get("slab", 0))
     ref = oracle_dhat(L, R, dmax, p)
     assert np.all(np.isfinite(d_hat))
     assert float(np.abs(d_hat - ref).max()) <= 1e-3
@@ -173,6 +179,41 @@ def test_backward_is_deterministic_and_batch_matches_single(ctx):
     s = run_gpu(ctx, L[1:2], R[1:2], G[1:2], M[1:2], 30, p)
     assert float(np.abs(s[0][0] - a[0][1]).max()) <= 1e-5
     assert_grad_close(s[2][0], 3.0 * a[2][1], "single vs batch g_left", rel=1e-4)
+
+
+def launch_step(ctx, L, R, G, M, dmax, p):
+    """Forward + loss + backward enqueued on the current stream, no wait."""
+    left = to_dev(L).requires_grad_(True)
+    right = to_dev(R).requires_grad_(True)
+    lambdas = torch.tensor((p.lambda_ad, p.lambda_census), dtype=torch.float32, device=DEV,
+                           requires_grad=True)
+    d_hat = soft_disparity(ctx, left, right, lambdas, dmax, sp_from(p))
+    loss = l1_loss(ctx, d_hat, to_dev(G.astype(np.int16)), to_dev(M.astype(np.uint8)))
+    loss.backward()
+    return d_hat, loss, left, right, lambdas
+
+
+def test_two_streams_equal_serial_runs(ctx):
+    """Forward + backward of two batches in flight on two streams at once
+    (each stream has its own plan and loss scratch) equal the same runs made
+    one after the other, bit for bit."""
+    A = float_pairs(2, 96, 40, 30, 560, noise=0.002)
+    B = float_pairs(1, 80, 48, 24, 570, noise=0.002)
+    p = osoft.SoftParams()
+    serial = [run_gpu(ctx, *A, 30, p), run_gpu(ctx, *B, 24, p)]
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for rep in range(2):
+        torch.cuda.synchronize()
+        live = []
+        for i, (case, dmax) in enumerate(((A, 30), (B, 24))):
+            with torch.cuda.stream(streams[i]):
+                live.append(launch_step(ctx, *case, dmax, p))
+        torch.cuda.synchronize()
+        for i, (d_hat, loss, left, right, lam) in enumerate(live):
+            got = (d_hat.detach().cpu().numpy(), float(loss.detach().cpu()[0]),
+                   left.grad.cpu().numpy(), right.grad.cpu().numpy(), lam.grad.cpu().numpy())
+            for u, v in zip(got, serial[i]):
+                assert np.array_equal(np.asarray(u), np.asarray(v)), (rep, i)
 
 
 def test_paper_size_batch_rows_match_oracle(ctx):

@@ -50,6 +50,53 @@ def test_lut_matches_brute_recomputation():
     assert ad.tolist() == bad and mc.tolist() == bmc
 
 
+def _golden_lut():
+    vals = {}
+    with open(os.path.join(GOLDEN, "lut_values.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, *v = line.split()
+                vals[k] = [int(t) for t in v]
+    return vals
+
+
+def test_lut_values_of_eq4_eq5_golden():
+    """Eq. 4-5 with lambda_AD = 0.3, lambda_MC = 2.3 (Sec. V), S = 1024: the
+    table entries and C_max stated in tests/golden/lut_values.txt."""
+    g = _golden_lut()
+    ad, mc = oracle.lut(P)
+    assert ad[:8].tolist() == g["lut_ad_first8"]
+    assert ad[253:].tolist() == g["lut_ad_last3"]
+    assert len(set(ad.tolist())) == g["lut_ad_distinct"][0]
+    assert mc.tolist() == g["lut_mc"]
+    assert int(ad[255]) + int(mc[6]) == g["c_max"][0]
+
+
+def test_lut_against_high_precision_exp():
+    """Every entry of both tables against S (1 - e^-t) evaluated in 60-digit
+    decimal arithmetic (a different exp than the oracle's libm), rounded half
+    up; no entry lies within 1e-6 of a rounding boundary, so the double
+    evaluation cannot round the other way."""
+    import decimal
+    import struct
+    ctx = decimal.Context(prec=60)
+
+    def f32(x):  # the float32 parameter widened exactly
+        return decimal.Decimal(struct.unpack("f", struct.pack("f", x))[0])
+
+    ad, mc = oracle.lut(P)
+    S = decimal.Decimal(P.cost_scale)
+    for table, n, denom in ((ad, 256, decimal.Decimal(255) * f32(P.lambda_ad)),
+                            (mc, 7, f32(P.lambda_mc))):
+        for a in range(n):
+            t = ctx.divide(decimal.Decimal(a), denom)
+            v = ctx.multiply(S, ctx.subtract(1, ctx.exp(-t)))
+            r = int((v + decimal.Decimal("0.5")).to_integral_value(rounding=decimal.ROUND_FLOOR))
+            assert int(table[a]) == r, (a, table[a], v)
+            frac = (v + decimal.Decimal("0.5")) - r
+            assert decimal.Decimal("1e-6") < frac < 1 - decimal.Decimal("1e-6"), (a, v)
+
+
 def test_lut_saturation_reading():
     """lambda_AD = 0.3 (Sec. V) on [0,1] brightness: the AD cost keeps growing
     over the whole 0..255 range (it would saturate at 2 grey levels on 0..255)."""
