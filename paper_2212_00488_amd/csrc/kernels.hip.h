@@ -330,7 +330,8 @@ struct TabArgs {
 // node, so it may be captured in a graph): clears nzero words at zero (the
 // padding of the pixel and arm planes must read 0; the kernels write the
 // image part) and writes the cost table, entry (h', 256 + diff) = LUT_AD[|diff|]
-// + LUT_MC[h'] for h' < kOutBias, else C_max; the pitch's spare columns 0.
+// + LUT_MC[h'] for h' < kOutBias, else C_max; column 0 and the pitch's spare
+// columns 0.
 // grid: any, block 256.
 __global__ void __launch_bounds__(256) k_plan_init(uint32_t* __restrict__ zero, size_t nzero,
                                                    uint16_t* __restrict__ tab, TabArgs t) {
@@ -340,8 +341,10 @@ __global__ void __launch_bounds__(256) k_plan_init(uint32_t* __restrict__ zero, 
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < (size_t)kTab; i += stride) {
     const int h = (int)i / kTabPitch, col = (int)i - h * kTabPitch;
     const int a = col < 256 ? 256 - col : col - 256;
-    tab[i] = col >= 511 ? (uint16_t)0
-                        : (h < kOutBias ? (uint16_t)(t.ad[a] + t.mc[h]) : t.cmax);
+    // columns 1..511 hold differences -255..255; column 0 (a difference of
+    // -256) and the spare columns are never read
+    tab[i] = (col == 0 || col > 511) ? (uint16_t)0
+                                     : (h < kOutBias ? (uint16_t)(t.ad[a] + t.mc[h]) : t.cmax);
   }
 }
 

@@ -129,6 +129,26 @@ def textured_shift_pair(W: int, H: int, shift: int, seed: int = 0):
     return left, right
 
 
+def extremes_pair(W: int, H: int, block: int = 8, seed: int = 0):
+    """Two independent images of ``block`` x ``block`` squares, each square
+    black (0) or white (255) with probability 1/2.
+
+    After the 2x downscale most half-resolution pixels are exactly 0 or 255,
+    so matches with brightness differences of -255, 0 and +255 are all
+    frequent: the ends of the absolute-difference table.
+    """
+    rng = np.random.default_rng(seed)
+    by, bx = (H + block - 1) // block, (W + block - 1) // block
+
+    def one():
+        cells = rng.integers(0, 2, size=(by, bx), dtype=np.uint8) * np.uint8(255)
+        img = np.repeat(np.repeat(cells, block, 0), block, 1)[:H, :W]
+        return np.ascontiguousarray(np.repeat(img[..., None], 3, 2))
+
+    left = one()
+    return left, one()
+
+
 # Workloads of the benchmark and parity suites (sizes and generator knobs).
 WORKLOADS = {
     "small_320x240_d32": dict(W=320, H=240, dmax=32, segments=6,

@@ -11,7 +11,8 @@ import numpy as np
 import pytest
 
 import oracle
-from paper_2212_00488_amd.synth import make_pair, textured_shift_pair, workload_pairs
+from paper_2212_00488_amd.synth import (extremes_pair, make_pair, textured_shift_pair,
+                                        workload_pairs)
 
 pytestmark = pytest.mark.gpu
 
@@ -119,6 +120,32 @@ def test_per_disparity_planes(sm, ctx, d):
     assert_same("cost_r", ctx.intermediate("cost_r_d", d), cR)
     assert_same("cax_r", ctx.intermediate("cax_r_d", d), oracle.agg_x(cR, ar))
     assert_same("ca_r", ctx.intermediate("ca_r_d", d), oracle.agg_y(oracle.agg_x(cR, ar), ar))
+
+
+@pytest.mark.parametrize("d", [0, 3, 12])
+def test_extreme_brightness_differences(sm, ctx, d):
+    """Black and white squares: half-res differences of exactly -255 and +255
+    (both ends of the LUT_AD index, Eq. 4) occur at every d; the cost and
+    window-sum planes and the whole map stay bit-exact."""
+    left, right = extremes_pair(240, 160, block=8, seed=21)
+    p = keep_params(sm)
+    got = run_gpu(ctx, left, right, 32, p)
+    q = oracle_params(p)
+    hl = oracle.downscale(oracle.gray(left))
+    hr = oracle.downscale(oracle.gray(right))
+    assert (hl.astype(int)[:, d:] - hr.astype(int)[:, : hl.shape[1] - d] == 255).any()
+    assert (hl.astype(int)[:, d:] - hr.astype(int)[:, : hl.shape[1] - d] == -255).any()
+    cl, cr = oracle.census(hl), oracle.census(hr)
+    al, ar = oracle.arms(hl, q), oracle.arms(hr, q)
+    ad, mc = oracle.lut(q)
+    cL = oracle.cost_left(hl, hr, cl, cr, d, q)
+    cR = oracle.cost_right_from_left(cL, d, int(ad[255]) + int(mc[6]))
+    assert_same("cost_l", ctx.intermediate("cost_l_d", d), cL)
+    assert_same("cost_r", ctx.intermediate("cost_r_d", d), cR)
+    assert_same("ca_l", ctx.intermediate("ca_l_d", d), oracle.agg_y(oracle.agg_x(cL, al), al))
+    assert_same("ca_r", ctx.intermediate("ca_r_d", d), oracle.agg_y(oracle.agg_x(cR, ar), ar))
+    exp = oracle.disparity(left, right, 32, q)
+    assert_same("out", got, exp["out"])
 
 
 @pytest.mark.parametrize("W,H,dmax,seed", [
