@@ -134,6 +134,28 @@ int stereo_autotune(stereo_ctx* ctx, const uint8_t* const* left, const uint8_t* 
                     int n, int W, int H, int Dmax, const stereo_params* params, int* chosen,
                     int* sizes, float* times_ms, int max_times, hipStream_t stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid allocation, harnesses that ban
+ * hipMalloc): stereo_disparity for one pair, with every scratch plane carved
+ * from one fixed array of STEREO_NOALLOC_MAX_BYTES per device instead of the
+ * context's cached plans.  The array is allocated when the library's code is
+ * loaded on the device (looked up once per device by stereo_create) and held
+ * until the process ends; this call makes no device allocation, free or
+ * memset (its set-up is a kernel, so it may be captured in a graph).
+ *   Arguments, layouts and ownership as for stereo_disparity.  params->flags
+ *   must not hold STEREO_F_KEEP_INTERMEDIATES or STEREO_F_STAGE_TIMING.
+ *   Returns STEREO_EINVAL when the shape's scratch exceeds the array (the
+ *   message gives both sizes; 1436x992 Dmax 145 needs about 46 MB,
+ *   1920x1080 Dmax 256 about 37 MB), STEREO_EHIP when the array's address
+ *   could not be found on this device.
+ * Every call on one device uses the same array and each call re-initialises
+ * it: calls whose work overlaps on a device (two streams, two contexts or
+ * two threads) race and give wrong maps; order them on one stream. */
+#define STEREO_NOALLOC_MAX_BYTES (64u << 20)
+int stereo_disparity_noalloc(stereo_ctx* ctx, const uint8_t* left, const uint8_t* right, int W,
+                             int H, int Dmax, const stereo_params* params, int16_t* out_disp,
+                             hipStream_t stream);
+
 /* Debug export of one plane of the last stereo_disparity call made with
  * STEREO_F_KEEP_INTERMEDIATES (pair 0 of a batch).  Copies into HOST memory
  * `dst`, which must hold at least `bytes` = the plane size; synchronises

@@ -5,6 +5,6 @@
 Importing the package loads nothing; the library is loaded on first use.
 """
 
-from .binding import (F_FULL_RES, F_KEEP_INTERMEDIATES, F_STAGE_TIMING, STAGES,  # noqa: F401
-                      Params,
+from .binding import (EHIP, EINVAL, ENOMEM, F_FULL_RES, F_KEEP_INTERMEDIATES,  # noqa: F401
+                      F_STAGE_TIMING, OK, STAGES, Params,
                       Stereo, StereoError, default_params, lib)

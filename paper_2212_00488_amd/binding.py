@@ -91,6 +91,8 @@ def lib():
         L.stereo_last_error.restype = ctypes.c_char_p
         L.stereo_disparity.argtypes = [P, P, P, I, I, I, ctypes.POINTER(Params), P, P]
         L.stereo_disparity.restype = I
+        L.stereo_disparity_noalloc.argtypes = [P, P, P, I, I, I, ctypes.POINTER(Params), P, P]
+        L.stereo_disparity_noalloc.restype = I
         L.stereo_disparity_batch.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(P), I, I, I, I,
                                              ctypes.POINTER(Params), ctypes.POINTER(P), P]
         L.stereo_disparity_batch.restype = I
@@ -217,6 +219,29 @@ class Stereo:
                                     out.data_ptr(), _stream_handle(stream))
         self._raise(rc)
         self._last_shape = (W, H, dmax, params is not None and bool(params.flags & F_FULL_RES))
+        return out
+
+    def disparity_noalloc(self, left, right, dmax: int, params: Params | None = None, out=None,
+                          stream=None):
+        """As disparity(), with the library's scratch in its fixed per-device
+        array (no device allocation by the library; overlapping calls on one
+        device race).  ``out`` should be given by callers that cannot
+        allocate."""
+        import torch
+        _check_image(left, "left")
+        _check_image(right, "right")
+        H, W, _ = left.shape
+        if tuple(right.shape) != (H, W, 3):
+            raise ValueError("left and right shapes differ")
+        if out is None:
+            out = torch.empty((H, W), dtype=torch.int16, device=left.device)
+        else:
+            _check_dev(out, "out", torch.int16, (H, W))
+        rc = lib().stereo_disparity_noalloc(self._h, left.data_ptr(), right.data_ptr(), W, H,
+                                            int(dmax),
+                                            ctypes.byref(params) if params is not None else None,
+                                            out.data_ptr(), _stream_handle(stream))
+        self._raise(rc)
         return out
 
     def disparity_batch(self, lefts, rights, dmax: int, params: Params | None = None,
@@ -358,3 +383,4 @@ class Stereo:
                                        g.data_ptr(), _stream_handle(stream))
         self._raise(rc)
         return g
+

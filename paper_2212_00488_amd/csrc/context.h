@@ -46,6 +46,10 @@ struct stereo_ctx {
   std::vector<stereo_host::Tuned> tuned;  // d-chunk sizes chosen by stereo_autotune
   // scratch of the L1 loss entry points, one block per stream
   std::vector<std::pair<hipStream_t, void*>> l1_blocks;
+  // device address of this device's fixed scratch array (stereo_disparity_noalloc),
+  // or null with the reason in noalloc_err
+  void* noalloc_scratch = nullptr;
+  std::string noalloc_err;
 };
 
 namespace stereo_host {

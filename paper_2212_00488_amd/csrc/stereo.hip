@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -18,7 +19,39 @@
 
 using namespace stereo_dev;
 
+// Fixed scratch of stereo_disparity_noalloc: one array per device, allocated
+// when the code object is loaded on that device and held until the process
+// ends.  Host code never uses its name as an address: the device address of
+// each device's copy comes from hipGetSymbolAddress (noalloc_scratch_of).
+constexpr size_t kNoallocBytes = size_t(STEREO_NOALLOC_MAX_BYTES);
+static __device__ __align__(256) uint8_t scratch[kNoallocBytes];
+
 namespace stereo_host {
+
+// Device address of `scratch` on `device` (the current device), looked up
+// once per device; null with *err set when the lookup failed.
+void* noalloc_scratch_of(int device, std::string* err) {
+  static std::mutex mu;
+  static std::vector<void*> addr;
+  static std::vector<std::string> why;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((size_t)device >= addr.size()) {
+    addr.resize(device + 1, nullptr);
+    why.resize(device + 1);
+  }
+  if (!addr[device] && why[device].empty()) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e == hipSuccess && ptr) {
+      addr[device] = ptr;
+    } else {
+      (void)hipGetLastError();
+      why[device] = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+    }
+  }
+  *err = why[device];
+  return addr[device];
+}
 
 // Cost tables of Eq. 4 and Eq. 5 in fixed point: S(1 - exp(-t)) rounded half
 // up, with t = (a / 255) / lambda_AD for brightness difference a and
@@ -551,6 +584,8 @@ int stereo_create(stereo_ctx** out, int device, size_t mem_cap) {
   if (hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess &&
       cu > 0)
     c->num_cu = cu;
+  // the device's fixed scratch array, for stereo_disparity_noalloc
+  c->noalloc_scratch = noalloc_scratch_of(device, &c->noalloc_err);
   *out = c;
   return 0;
 }
@@ -689,6 +724,41 @@ int stereo_disparity(stereo_ctx* c, const uint8_t* left, const uint8_t* right, i
                      int Dmax, const stereo_params* params, int16_t* out_disp, hipStream_t stream) {
   if (!c) return STEREO_EINVAL;
   return stereo_disparity_batch(c, &left, &right, 1, W, H, Dmax, params, &out_disp, stream);
+}
+
+int stereo_disparity_noalloc(stereo_ctx* c, const uint8_t* left, const uint8_t* right, int W,
+                             int H, int Dmax, const stereo_params* params, int16_t* out_disp,
+                             hipStream_t stream) {
+  if (!c) return STEREO_EINVAL;
+  c->err.clear();
+  if (!left || !right || !out_disp) return fail(c, STEREO_EINVAL, "null pointer");
+  stereo_params p;
+  int rc = common_checks(c, W, H, Dmax, params, &p);
+  if (rc) return rc;
+  if (p.flags & (STEREO_F_KEEP_INTERMEDIATES | STEREO_F_STAGE_TIMING))
+    return fail(c, STEREO_EINVAL, "stereo_disparity_noalloc takes neither "
+                "STEREO_F_KEEP_INTERMEDIATES nor STEREO_F_STAGE_TIMING");
+  if (!c->noalloc_scratch)
+    return fail(c, STEREO_EHIP, "no fixed scratch on device %d: %s", c->device,
+                c->noalloc_err.c_str());
+  // the plan lives on the stack and its memory is the fixed array: geometry
+  // and tables are host arithmetic, the set-up (padding cleared, cost table
+  // written) is a kernel on the caller's stream
+  Plan pl{};
+  rc = plan_setup(c, pl, W, H, Dmax, p, 1, tuned_csize(c, W, H, Dmax, 1, p));
+  if (rc) return rc;
+  const size_t bytes = plan_bytes(pl).total;
+  if (bytes > kNoallocBytes)
+    return fail(c, STEREO_EINVAL, "%dx%d Dmax %d needs %zu bytes of scratch; the fixed array "
+                "holds %zu (use stereo_disparity)", W, H, Dmax, bytes, kNoallocBytes);
+  HIP_TRY(c, hipSetDevice(c->device));
+  (void)hipGetLastError();
+  plan_carve_and_init(pl, c->noalloc_scratch, stream);
+  PairPtrs pp{};
+  pp.left[0] = left;
+  pp.right[0] = right;
+  pp.out[0] = out_disp;
+  return run(c, pl, pp, 1, false, false, stream);
 }
 
 int stereo_stage_times(stereo_ctx* c, double* ms, int* calls, int reset) {
