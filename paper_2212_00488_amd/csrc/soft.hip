@@ -41,7 +41,6 @@ struct SoftPlan {
   float4* pc = nullptr;        // [n][Y][X]
   float* gca = nullptr;        // [nds][n][Y][X]
   float* gcax = nullptr;       // [nds][n][Y][X] dL/dCA_x (the gca planes then hold t)
-  int ring = 64;               // rows of k_soft_tcol's difference-array ring
   float* g_half = nullptr;     // [2n][Y][X]
   float2* lam_part = nullptr;  // [lam_count]
   uint64_t last_use = 0;
@@ -127,7 +126,6 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
   pl->nds = p.slab > 0 ? std::min(p.slab, D)
                        : (int)std::max<size_t>(1, std::min<size_t>(D, kSlabBudget / (2 * n * npix * 4)));
   pl->nbands_tr = (Y + kSoftBR - 1) / kSoftBR;
-  while (pl->ring < 2 * p.arm_y + 2) pl->ring *= 2;
   const int nslab = (D + pl->nds - 1) / pl->nds;
   pl->lam_count = (size_t)nslab * pl->nds * n * pl->nstrips * pl->nbands_tr;
 
@@ -172,16 +170,11 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
   pl->lam_part = carve<float2>(cur, pl->lam_count);
   // zero padding of the arm and pixel planes (kernels write the image part),
   // ordered on the plan's stream: no other stream is stalled
-  e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_soft_tcol),
-                          hipFuncAttributeMaxDynamicSharedMemorySize,
-                          4 * pl->ring * 64 * (int)sizeof(float));
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, s, reinterpret_cast<float*>(pl->arms),
-                       nimg * Y * pl->XA, 0.f);
-    hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, s, reinterpret_cast<float*>(pl->sp),
-                       nimg * Y * pl->XS * 2, 0.f);
-    e = hipGetLastError();
-  }
+  hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, s, reinterpret_cast<float*>(pl->arms),
+                     nimg * Y * pl->XA, 0.f);
+  hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, s, reinterpret_cast<float*>(pl->sp),
+                     nimg * Y * pl->XS * 2, 0.f);
+  e = hipGetLastError();
   if (e != hipSuccess) {
     (void)hipFree(pl->block);
     delete pl;
@@ -371,9 +364,10 @@ int stereo_soft_backward(stereo_ctx* c, const float* left, const float* right, i
     const int dhi = std::min(pl->D, dlo + pl->nds), nds = dhi - dlo;
     const int cs = best_chunk_size(groups, nds, pl->rows, c->num_cu);
     launch_soft_agg<true>(*pl, soft_args(*pl, lambdas, dlo, dhi, cs), stream);
-    hipLaunchKernelGGL(k_soft_tcol, dim3((X + 63) / 64, (nds + 3) / 4, pl->n), dim3(64, 4),
-                       4 * pl->ring * 64 * sizeof(float), stream, pl->gca, pl->arms, X, Y, pl->XA,
-                       pl->p.arm_y, pl->ring, pl->n, nds, pl->gcax);
+    const int tb = pl->p.arm_y <= 31 ? kTcolBand : kTcolBand / 2;
+    hipLaunchKernelGGL(k_soft_tcol, dim3((X + 63) / 64, (Y + tb - 1) / tb, nds * pl->n),
+                       dim3(256), 0, stream, pl->gca, pl->arms, X, Y, pl->XA, pl->p.arm_y, pl->n,
+                       pl->gcax);
     TrArgs ta{};
     ta.gcax = pl->gcax; ta.arms = pl->arms; ta.sp = pl->sp; ta.lam = lambdas; ta.t = pl->gca;
     ta.lam_part = pl->lam_part + lam_off;

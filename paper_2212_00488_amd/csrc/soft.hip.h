@@ -44,7 +44,6 @@ namespace stereo_dev {
 namespace {
 
 constexpr int kSoftBR = 16;  // output rows per k_soft_tr workgroup
-constexpr int kTcolBatch = 24;  // source rows per batch of loads in k_soft_tcol
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
@@ -434,76 +433,102 @@ __global__ void __launch_bounds__(256) k_soft_bprep(const float* __restrict__ in
 }
 
 // ------------------------------------------------------------ k_soft_tcol
-// Transpose of the vertical window sum (Eq. 8) for one disparity, one column
-// per lane, streaming down the column once:
+// Transpose of the vertical window sum (Eq. 8) for one disparity over a band
+// of kTcolBand output rows of a 64-column strip:
 //   CA(x,y) = sum_{s=-M(x,y)}^{N(x,y)} CA_x(x,y+s)  gives
-//   dL/dCA_x(x,y') = sum of dL/dCA(x,y) over the y whose window holds y',
-// a difference array (+g at y - M, -g at y + N + 1) and a prefix down the
-// column.  A source row y only touches rows y - arm_y .. y + arm_y + 1, so
-// the array lives in an LDS ring of `ring` >= 2 arm_y + 2 rows per column:
-// after source y, row y - arm_y can receive nothing more, is added to the
-// running prefix, written out and its slot cleared.  Each lane owns its
-// column's ring, so the updates need no atomics.  Loads of kTcolBatch rows
-// are issued together, the next batch's before this one's updates.
-// grid: (ceil(X/64), ceil(nds/4), n), block (64, 4) = one disparity per
-// wave; dynamic LDS 4 * ring * 64 floats.
+//   dL/dCA_x(x,y') = sum of dL/dCA(x,y) over the y whose window holds y'.
+// The band's rows y' in [Y0, Y0 + B) can only be reached from sources y in
+// [Y0 - arm_y, Y0 + B + arm_y); each source's window, clipped to the band,
+// becomes a difference array (+g at its first row, -g after its last) and a
+// prefix down the column gives the sums.  The difference array is integer
+// fixed point with a per-column scale 2^k, k = 23 - e where 2^(e-1) <= the
+// column's largest |g| < 2^e: each term is below 2^23 and a sum of at most
+// 2 arm_y + 1 <= 127 terms below 2^30, so LDS integer atomic adds give exact
+// sums in any order (the result does not depend on scheduling) and each
+// term is rounded to 2^(e-24), the float resolution of the column's largest
+// value.  Thread (wave w, lane l) takes column x0 + l and the source rows
+// Y0 - arm_y + w + 4 i, all loads issued together and held in registers.
+// grid: (ceil(X/64), ceil(Y/B), nds * n), block 256; B = kTcolBand for
+// arm_y <= 31, else kTcolBand / 2 (the sources then still fit 48 per thread).
+constexpr int kTcolBand = 128;
+constexpr int kTcolSrc = 48;  // source rows per thread at most
+
+__device__ __forceinline__ int tcol_band(int arm_y) { return arm_y <= 31 ? kTcolBand : kTcolBand / 2; }
+
 __global__ void __launch_bounds__(256) k_soft_tcol(const float* __restrict__ gca,
                                                    const uint32_t* __restrict__ arms, int X,
-                                                   int Y, int XA, int arm_y, int ring, int npair,
-                                                   int nds, float* __restrict__ gcax) {
-  extern __shared__ float s_ring[];
-  const int lane = threadIdx.x, wave = threadIdx.y;
-  const int x = blockIdx.x * 64 + lane, dj = blockIdx.y * 4 + wave, pair = blockIdx.z;
-  if (dj >= nds) return;  // a whole wave; the kernel has no barrier
-  float* rg = s_ring + (size_t)wave * ring * 64 + lane;
-  for (int i = 0; i < ring; ++i) rg[i * 64] = 0.f;
-  const int mask = ring - 1;
+                                                   int Y, int XA, int arm_y, int npair,
+                                                   float* __restrict__ gcax) {
+  __shared__ int s_d[kTcolBand + 1][64];
+  __shared__ float s_max[4][64];
+  __shared__ int s_tot[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int B = tcol_band(arm_y);
+  const int x = blockIdx.x * 64 + lane, Y0 = blockIdx.y * B;
+  const int dj = blockIdx.z / npair, pair = blockIdx.z - dj * npair;
+  const int Y1 = min(Y, Y0 + B);
   const bool xv = x < X;
   const size_t plane = (size_t)X * Y;
-  const float* g = gca + ((size_t)dj * npair + pair) * plane + x;
-  const uint32_t* am = arms + (size_t)(2 * pair) * Y * XA + x;
-  float* out = gcax + ((size_t)dj * npair + pair) * plane + x;
-  float carry = 0.f;
-  auto finalize = [&](int f) {
-    float* slot = rg + (f & mask) * 64;
-    carry += *slot;
-    *slot = 0.f;
-    if (xv) out[(size_t)f * X] = carry;
-  };
-  float gv[2][kTcolBatch];
-  uint32_t av[2][kTcolBatch];
-  auto fetch = [&](int y, int buf) {
+  const float* g = gca + ((size_t)dj * npair + pair) * plane;
+  const uint32_t* am = arms + (size_t)(2 * pair) * Y * XA;
+  const int ys = max(0, Y0 - arm_y), ye = min(Y, Y1 + arm_y);
+  // sources y = ys + wave + 4 i < ye; loads at clamped rows, masked after
+  float gv[kTcolSrc];
+  uint32_t av[kTcolSrc];
 #pragma unroll
-    for (int i = 0; i < kTcolBatch; ++i) {
-      const int yy = min(y + i, Y - 1);
-      gv[buf][i] = xv ? g[(size_t)yy * X] : 0.f;
-      av[buf][i] = xv ? am[(size_t)yy * XA] : 0u;
-    }
-  };
-  auto scatter = [&](int y, int buf) {
-#pragma unroll
-    for (int i = 0; i < kTcolBatch; ++i) {
-      const int yy = y + i;
-      if (yy >= Y) break;
-      const float v = gv[buf][i];
-      const uint32_t m = av[buf][i];
-      if (v != 0.f) {
-        rg[((yy - (int)((m >> 16) & 255u)) & mask) * 64] += v;
-        const int e = yy + (int)(m >> 24) + 1;
-        if (e < Y) rg[(e & mask) * 64] -= v;
-      }
-      if (yy - arm_y >= 0) finalize(yy - arm_y);
-    }
-  };
-  fetch(0, 0);
-  for (int y = 0; y < Y; y += 2 * kTcolBatch) {
-    if (y + kTcolBatch < Y) fetch(y + kTcolBatch, 1);
-    scatter(y, 0);
-    if (y + kTcolBatch >= Y) break;
-    if (y + 2 * kTcolBatch < Y) fetch(y + 2 * kTcolBatch, 0);
-    scatter(y + kTcolBatch, 1);
+  for (int i = 0; i < kTcolSrc; ++i) {
+    const int y = min(ys + wave + 4 * i, ye - 1);
+    gv[i] = xv ? g[(size_t)y * X + x] : 0.f;
+    av[i] = am[(size_t)y * XA + min(x, XA - 1)];
   }
-  for (int f = max(0, Y - arm_y); f < Y; ++f) finalize(f);
+  for (int i = threadIdx.x; i < (B + 1) * 64; i += 256) (&s_d[0][0])[i] = 0;
+  float mx = 0.f;
+#pragma unroll
+  for (int i = 0; i < kTcolSrc; ++i)
+    if (ys + wave + 4 * i < ye) mx = fmaxf(mx, fabsf(gv[i]));
+  s_max[wave][lane] = mx;
+  __syncthreads();
+  const float cmax = fmaxf(fmaxf(s_max[0][lane], s_max[1][lane]), fmaxf(s_max[2][lane], s_max[3][lane]));
+  int e = 0;
+  (void)frexpf(cmax, &e);
+  const float up = cmax > 0.f ? ldexpf(1.f, 23 - e) : 0.f;
+#pragma unroll
+  for (int i = 0; i < kTcolSrc; ++i) {
+    const int y = ys + wave + 4 * i;
+    if (y < ye && gv[i] != 0.f) {
+      const int q = (int)rintf(gv[i] * up);
+      const int M = (int)((av[i] >> 16) & 255u), N = (int)(av[i] >> 24);
+      const int lo = max(y - M, Y0), hi = min(y + N, Y1 - 1);
+      if (lo <= hi) {
+        atomicAdd(&s_d[lo - Y0][lane], q);
+        if (hi + 1 < Y1) atomicAdd(&s_d[hi + 1 - Y0][lane], -q);
+      }
+    }
+  }
+  __syncthreads();
+  // prefix down the column: wave w takes rows w * B/4 .. (w+1) * B/4 - 1,
+  // its running sum kept per row, then the totals of the waves above
+  const int rpw = B / 4, r0 = wave * rpw;
+  int run = 0;
+  int loc[kTcolBand / 4];
+#pragma unroll
+  for (int i = 0; i < kTcolBand / 4; ++i) {
+    if (i < rpw) run += s_d[r0 + i][lane];
+    loc[i] = run;
+  }
+  s_tot[wave][lane] = run;
+  __syncthreads();
+  int off = 0;
+#pragma unroll
+  for (int w = 0; w < 3; ++w) off += w < wave ? s_tot[w][lane] : 0;
+  if (!xv) return;
+  const float down = cmax > 0.f ? ldexpf(1.f, e - 23) : 0.f;
+  float* out = gcax + ((size_t)dj * npair + pair) * plane + x;
+#pragma unroll
+  for (int i = 0; i < kTcolBand / 4; ++i) {
+    const int y = Y0 + r0 + i;
+    if (i < rpw && y < Y1) out[(size_t)y * X] = (float)(loc[i] + off) * down;
+  }
 }
 
 // ------------------------------------------------------------- k_soft_tr
@@ -517,11 +542,12 @@ __global__ void __launch_bounds__(256) k_soft_tcol(const float* __restrict__ gca
 //   dL/dlambda_AD     += dL/dC * (-E a / lambda_AD^2)
 //   dL/dlambda_census += dL/dC * (-e^{-H/lambda_census} H / lambda_census^2)
 // for x - d >= 0 (the constant cost of x - d < 0 has no derivative).
-// The band's dL/dCA_x and arms over columns x0 - 32 .. x0 + 95 (every column
-// whose horizontal window reaches the strip, arm_x <= 31) are staged in LDS;
-// a lane per band row walks a quarter of those columns into its wave's
-// partial difference array, and a DPP scan over the summed partials gives
-// dL/dC.
+// The sources of a row are the columns x0 - 32 .. x0 + 95 (every column
+// whose horizontal window reaches the strip, arm_x <= 31): the 16 lanes of
+// a DPP row take 8 consecutive source columns each of one band row.  The
+// difference arrays are integer fixed point with a per-row scale (as in
+// k_soft_tcol: terms below 2^23, sums of at most 63 terms below 2^29), added
+// with LDS integer atomics, so the result does not depend on their order.
 // grid: (strips * bands, nds, n), block 256.
 struct TrArgs {
   const float* gcax;        // [nds][n][Y][X] dL/dCA_x
@@ -533,13 +559,20 @@ struct TrArgs {
   int X, Y, XS, pads, XA, npair, dlo, nstrips, nbands;
 };
 
+// Maximum over the 16 lanes of each DPP row (every lane receives it).
+__device__ __forceinline__ float row16_max(float v) {
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false)));  // row_ror:8
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false)));  // row_ror:4
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4e, 0xf, 0xf, false)));   // quad_perm 2,3,0,1
+  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xb1, 0xf, 0xf, false)));   // quad_perm 1,0,3,2
+  return v;
+}
+
 __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
   constexpr int BR = kSoftBR;
-  // staged tiles (row pitch 129: a lane per row reads one column without
-  // bank conflicts) and four partial row difference arrays, one per wave
-  __shared__ float s_g[BR][129];
-  __shared__ uint16_t s_mn[BR][130];
-  __shared__ float s_d2[4][BR][65];
+  static_assert(BR == 16, "one band row per 16 threads");
+  __shared__ int s_d[BR][65];
+  __shared__ float s_down[BR];
   __shared__ float2 s_red[4];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int strip = blockIdx.x % a.nstrips, band = blockIdx.x / a.nstrips;
@@ -549,28 +582,44 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
   const size_t plane = (size_t)X * Y;
   const float* g = a.gcax + ((size_t)dj * a.npair + pair) * plane;
   const uint32_t* arm = a.arms + (size_t)(2 * pair) * Y * a.XA;
-  // stage dL/dCA_x and the horizontal arms (m | n << 8) of columns
-  // x0 - 32 .. x0 + 95: thread t takes column t & 127 of rows (t >> 7) + 2 k,
-  // all loads issued together
-  {
-    const int c = t & 127, col = x0 - 32 + c, r0 = t >> 7;
-    const bool cv = col >= 0 && col < X;
-    float v[BR / 2];
-    uint32_t m[BR / 2];
+  // source columns x0 - 32 + 8 j .. + 7 (j = t & 15) of band row t >> 4
+  const int sr = t >> 4, sj = t & 15, sy = y0 + sr;
+  const bool yin = sy < Y;
+  const int ysafe = min(sy, Y - 1);
+  float gv[8];
+  uint32_t mv[8];
 #pragma unroll
-    for (int k = 0; k < BR / 2; ++k) {
-      const int y = y0 + r0 + 2 * k;
-      const bool in = cv && y < Y;
-      v[k] = in ? g[(size_t)y * X + col] : 0.f;
-      m[k] = in ? arm[(size_t)y * a.XA + col] : 0u;
-    }
+  for (int k = 0; k < 8; ++k) {
+    const int col = x0 - 32 + 8 * sj + k;
+    const bool cv = yin && col >= 0 && col < X;
+    const int cc = min(max(col, 0), X - 1);
+    const float v = g[(size_t)ysafe * X + cc];
+    const uint32_t m = arm[(size_t)ysafe * a.XA + cc];
+    gv[k] = cv ? v : 0.f;
+    mv[k] = m;
+  }
+  for (int i = t; i < BR * 65; i += 256) (&s_d[0][0])[i] = 0;
+  float mx = 0.f;
 #pragma unroll
-    for (int k = 0; k < BR / 2; ++k) {
-      s_g[r0 + 2 * k][c] = v[k];
-      s_mn[r0 + 2 * k][c] = (uint16_t)(m[k] & 0xffffu);
+  for (int k = 0; k < 8; ++k) mx = fmaxf(mx, fabsf(gv[k]));
+  mx = row16_max(mx);
+  int e = 0;
+  (void)frexpf(mx, &e);
+  const float up = mx > 0.f ? ldexpf(1.f, 23 - e) : 0.f;
+  if (sj == 0) s_down[sr] = mx > 0.f ? ldexpf(1.f, e - 23) : 0.f;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    if (gv[k] != 0.f) {
+      const int q = (int)rintf(gv[k] * up);
+      const int col = x0 - 32 + 8 * sj + k;
+      const int lo = col - (int)(mv[k] & 255u) - x0, hi = col + (int)((mv[k] >> 8) & 255u) + 1 - x0;
+      if (hi > 0 && lo < 64) {
+        atomicAdd(&s_d[sr][max(lo, 0)], q);
+        if (hi < 64) atomicAdd(&s_d[sr][hi], -q);
+      }
     }
   }
-  for (int i = t; i < 4 * BR * 65; i += 256) (&s_d2[0][0][0])[i] = 0.f;
   // operands of the cost derivative at the rows r = wave + 4 i of this wave
   const float lam_ad = a.lam[0], lam_c = a.lam[1];
   const float k2 = 255.f * 1.4426950408889634f / lam_ad;
@@ -591,33 +640,12 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
     pr_[i] = (xin && dv) ? spr[(size_t)y * a.XS + x - d] : make_uint2(0u, 0u);
   }
   __syncthreads();
-  // row difference arrays: lane r (< BR) of wave w walks the source columns
-  // 32 w .. 32 w + 31 of tile row r (+g at x - m, -g at x + n + 1, clipped to
-  // the strip), into the wave's own partial array: no atomics
-  if (lane < BR) {
-    const int r = lane;
-    float* dr = &s_d2[wave][r][0];
-#pragma unroll 4
-    for (int c = 32 * wave; c < 32 * wave + 32; ++c) {
-      const float gx = s_g[r][c];
-      const uint32_t mn = s_mn[r][c];
-      const int col = x0 - 32 + c;
-      const int lo = col - (int)(mn & 255u) - x0, hi = col + (int)(mn >> 8) + 1 - x0;
-      if (gx != 0.f && hi > 0 && lo < 64) {
-        dr[max(lo, 0)] += gx;
-        if (hi < 64) dr[hi] -= gx;
-      }
-    }
-  }
-  __syncthreads();
-  // prefix along each row (the four partials summed in a fixed order), then
-  // the cost derivatives
+  // prefix along each row, then the cost derivatives
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
     const int r = wave + 4 * i, y = y0 + r;
     if (y >= Y) break;
-    const float dsum = (s_d2[0][r][lane] + s_d2[1][r][lane]) + (s_d2[2][r][lane] + s_d2[3][r][lane]);
-    const float gc = wave_scan_incl_f(dsum);
+    const float gc = (float)(int)wave_scan_incl((uint32_t)s_d[r][lane]) * s_down[r];
     if (xin) {
       float tv = 0.f;
       if (dv) {
