@@ -31,22 +31,25 @@ if ROOT not in sys.path:
 WORKLOAD = "paper_1436x992_d145"
 W, H, DMAX = 1436, 992, 145
 PAPER_FPS = 40.0  # Table II / abstract, GTX 780 Ti, Adirondack at this size
-# Peak integer VALU rate: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
-PEAK_INT_OPS = 256 * 4 * 16 * 2.4e9
+# Spec-sheet rates, reported beside the measured ones: 32-bit VALU 128 lane
+# operations per clock per CU (the 157.3 TFLOP/s fp32 vector rate counts an
+# FMA as two) x 256 CUs x 2.4 GHz; LDS 256 B per clock per CU (what the
+# ds_read_b128 probe measures on gfx950) x 256 CUs x 2.4 GHz; HBM3E 8 TB/s.
+SPEC_INT_OPS = 128 * 256 * 2.4e9
+SPEC_LDS_BYTES = 256 * 256 * 2.4e9
+SPEC_HBM_BYTES = 8.0e12
 # Work model of the fused cost / aggregation / WTA kernel per half-res
 # evaluation e = (x, y, d), both bases, with O(1) window sums:
+#   LDS bytes 48 (the scored figure): per base, the row-prefix store 4, the
+#   two CA_x window-end loads 8, the column-prefix store 4 and the two CA
+#   window-end loads 8;
 #   integer VALU ops ~ 40: per base, the cost of the pixel pair (difference,
 #   xor, popcount, table index: 4) evaluated on the strip and its arm halo,
 #   the row-prefix scan step and add, the two window ends and difference of
 #   CA_x, the column-prefix add, the two window ends and difference of CA,
-#   and the packed-key compare (about 20 per base);
-#   LDS bytes 48: per base, the row-prefix store 4, the two CA_x window-end
-#   loads 8, the column-prefix store 4 and the two CA window-end loads 8.
-OPS_PER_EVAL = 40
+#   and the packed-key compare (about 20 per base).
 LDS_BYTES_PER_EVAL = 48
-# LDS bandwidth figure used beside it: 128 B per clock per CU (the CDNA3
-# rate; a lower bound for gfx950) x 256 CUs x 2.4 GHz.
-PEAK_LDS_BYTES = 128 * 256 * 2.4e9
+OPS_PER_EVAL = 40
 
 
 def parse():
@@ -65,6 +68,9 @@ def parse():
                     help="timed steps of the 8 x 1920x1080 batch (0 skips it)")
     ap.add_argument("--soft-steps", type=int, default=10,
                     help="timed steps of the differentiable head (0 skips it)")
+    ap.add_argument("--calibrate-peaks", action="store_true",
+                    help="only measure the device's LDS-read, integer-VALU and copy peak "
+                         "rates with the library's probes, print them and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run plain device copies of MIB MiB (reference for the "
                          "FETCH_SIZE / WRITE_SIZE counters) and exit")
@@ -72,6 +78,7 @@ def parse():
 
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_match_traffic.json")
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_match_counters.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2212_00488_amd", "csrc", "kernels.hip.h")
 
 
@@ -120,6 +127,19 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
+def measured_valu_instructions():
+    """VALU wave instructions per k_match launch from the committed counter
+    summary, or None when the kernel source has changed since."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_source_sha256_16") != kernel_source_hash():
+        return None
+    return t.get("SQ_INSTS_VALU_per_dispatch")
+
+
 def calibrate_copy(mib: int):
     import torch
     n = mib * (1 << 20)
@@ -138,22 +158,47 @@ def percentile(v, q):
     return v[i]
 
 
-def cpu_baseline(pair, seconds):
-    """The oracle as it stands, on this host's cores, for ~`seconds`."""
+def _oracle_fps(pair, w, h, dmax, seconds, min_frames=1):
     import oracle
-    oracle.lib()
     frames, t0 = 0, time.perf_counter()
     while True:
-        oracle.disparity(pair.left, pair.right, DMAX)
+        oracle.disparity(pair.left, pair.right, dmax)
         frames += 1
         el = time.perf_counter() - t0
-        if el >= seconds:
+        if el >= seconds and frames >= min_frames:
             break
     fps = frames / el
-    return {"value": round(fps, 4), "unit": "frames/s", "cores": oracle.num_threads(),
-            "kind": "oracle",
-            "sample": f"{frames} full {W}x{H} Dmax={DMAX} frames in {el:.1f} s",
-            "mde_per_s": round(W * H * DMAX * fps / 1e6, 2)}
+    return {"frames_per_s": round(fps, 4), "mde_per_s": round(w * h * dmax * fps / 1e6, 2),
+            "sample": f"{frames} full {w}x{h} Dmax={dmax} frames in {el:.1f} s"}
+
+
+def cpu_baseline(pair, seconds):
+    """The oracle as it stands, on this host's cores: all OpenMP threads on
+    ~`seconds` of the paper-sized workload (the reported value), then one
+    thread on one frame of it, and both thread counts on the 320x240 Dmax 32
+    workload for a second each."""
+    import oracle
+    from paper_2212_00488_amd.synth import workload_pairs
+    oracle.lib()
+    cores = oracle.num_threads()
+    main = _oracle_fps(pair, W, H, DMAX, seconds)
+    small = workload_pairs("small_320x240_d32")[0]
+    res = {"value": main["frames_per_s"], "unit": "frames/s", "cores": cores, "kind": "oracle",
+           "sample": main["sample"], "mde_per_s": main["mde_per_s"],
+           "threads": {str(cores): {"paper_1436x992_d145": main,
+                                    "small_320x240_d32": _oracle_fps(small, 320, 240, 32, 1.0)}}}
+    try:
+        import platform
+        with open("/proc/cpuinfo") as f:
+            names = [ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")]
+        res["host_cpu"] = names[0] if names else platform.processor()
+    except OSError:
+        pass
+    oracle.set_num_threads(1)
+    res["threads"]["1"] = {"paper_1436x992_d145": _oracle_fps(pair, W, H, DMAX, 0.0),
+                           "small_320x240_d32": _oracle_fps(small, 320, 240, 32, 1.0)}
+    oracle.set_num_threads(cores)
+    return res
 
 
 def batch_leg(sm, steps):
@@ -264,56 +309,72 @@ def soft_leg(sm, steps):
 
 
 SERVE_SHAPES = [(640, 480, 64), (1436, 992, 145), (1920, 1080, 256), (2872, 1984, 290)]
-SERVE_RATE = 120.0  # requests per second, Poisson arrivals
+SERVE_RATE = 120.0        # requests per second, Poisson arrivals (the workload's rate)
+SERVE_RATE_HIGH = 4000.0  # an offered rate above what the device serves: saturation
 
 
-def serve_leg(n_requests):
-    """Mixed-resolution request stream through the serving runtime: shapes
-    drawn uniformly from SERVE_SHAPES, exponential inter-arrival times at
-    SERVE_RATE (arrival seed 600), 4 slots, admission budget of two of the
-    largest cost volumes.  Inputs come from a pool of two synthetic pairs per
-    shape (seeds 10000 + 10 k + j) in page-locked host memory; each request
-    uploads its pair, runs the resident graph and copies the map back into a
-    page-locked host output buffer, all inside the measured latency."""
-    import numpy as np
+def serve_pool():
+    """Two synthetic pairs per served shape (seeds 10000 + 10 k + j) in
+    page-locked host memory, and the oracle's map of each: every served map
+    is checked against the map of its pool frame."""
+    import oracle
     import torch
-    from paper_2212_00488_amd.serve import Server, replay
     from paper_2212_00488_amd.synth import make_pair
 
-    rng = np.random.default_rng(600)
-    kinds = rng.integers(0, len(SERVE_SHAPES), size=n_requests)
-    which = rng.integers(0, 2, size=n_requests)
-    arrivals = np.cumsum(rng.exponential(1.0 / SERVE_RATE, size=n_requests))
-    pool = {}
+    pool, ref = {}, {}
     for k, (w, h, dm) in enumerate(SERVE_SHAPES):
         for j in range(2):
             p = make_pair(w, h, dm, segments=40, textureless=0.1, seed=10000 + 10 * k + j)
-            lt = torch.from_numpy(p.left).pin_memory()
-            rt = torch.from_numpy(p.right).pin_memory()
-            pool[(k, j)] = (lt, rt)
+            pool[(k, j)] = (torch.from_numpy(p.left).pin_memory(),
+                            torch.from_numpy(p.right).pin_memory())
+            ref[(k, j)] = oracle.disparity(p.left, p.right, dm)["out"]
+    return pool, ref
+
+
+def serve_leg(n_requests, rate, pool, ref, arrival_seed=600):
+    """Mixed-resolution request stream through the serving runtime: shapes
+    drawn uniformly from SERVE_SHAPES, exponential inter-arrival times at
+    `rate` (arrival seed 600), 4 slots, batches of up to 8 frames of one
+    shape, admission budget of two of the largest cost volumes.  Each
+    request uploads its pair, runs the resident graph and copies the map
+    back into a page-locked host output buffer, all inside the measured
+    latency; every map is compared with the oracle's."""
+    import numpy as np
+    import torch
+    from paper_2212_00488_amd.serve import Server, replay
+
+    rng = np.random.default_rng(arrival_seed)
+    kinds = rng.integers(0, len(SERVE_SHAPES), size=n_requests)
+    which = rng.integers(0, 2, size=n_requests)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=n_requests))
     frames = [(pool[(k, j)][0].numpy(), pool[(k, j)][1].numpy()) for k, j in zip(kinds, which)]
     dmaxes = [SERVE_SHAPES[k][2] for k in kinds]
     big = max(((w + 1) // 2) * ((h + 1) // 2) * ((d + 1) // 2) * 4 for w, h, d in SERVE_SHAPES)
-    srv = Server(0, slots=4, mem_budget=2 * big)
+    srv = Server(0, slots=4, mem_budget=2 * big, max_batch=8)
     # warm: one frame of each shape on each slot builds the resident plans and graphs
     warm = [(pool[(k, 0)][0].numpy(), pool[(k, 0)][1].numpy()) for k in range(4) for _ in range(4)]
     replay(srv, warm, np.zeros(len(warm)), [SERVE_SHAPES[k][2] for k in range(4) for _ in range(4)])
     outs = [torch.empty(f[0].shape[:2], dtype=torch.int16).pin_memory().numpy() for f in frames]
     rep, _ = replay(srv, frames, arrivals, dmaxes, outs=outs)
     srv.close()
+    bad = sum(not np.array_equal(o, ref[(k, j)]) for o, k, j in zip(outs, kinds, which))
     lat = rep.latency_ms
+    batch = np.array([r["batch"] for r in rep.results])
     per_shape = {}
     for k, (w, h, d) in enumerate(SERVE_SHAPES):
         m = kinds == k
         per_shape[f"{w}x{h}_d{d}"] = {"n": int(m.sum()),
                                       "p50_ms": round(float(np.percentile(lat[m], 50)), 3),
                                       "p99_ms": round(float(np.percentile(lat[m], 99)), 3)}
-    return {"requests": n_requests, "rate_per_s": SERVE_RATE, "slots": 4,
+    return {"requests": n_requests, "offered_rate_per_s": rate, "slots": 4, "max_batch": 8,
             "throughput_per_s": round(rep.throughput, 2),
             "latency_ms": {"p50": round(float(np.percentile(lat, 50)), 3),
                            "p99": round(float(np.percentile(lat, 99)), 3),
                            "max": round(float(lat.max()), 3)},
             "per_shape": per_shape,
+            "mean_batch": round(float(batch.mean()), 3),
+            "frames_in_batches_of": {str(b): int((batch == b).sum()) for b in (1, 2, 4, 8)},
+            "maps_differing_from_oracle": int(bad),
             "host_memory": "page-locked inputs and outputs, both copies included"}
 
 
@@ -321,6 +382,14 @@ def main():
     args = parse()
     if args.calibrate_copy:
         calibrate_copy(args.calibrate_copy)
+        return
+    if args.calibrate_peaks:
+        import paper_2212_00488_amd as sm
+        pk = sm.binding.measure_peaks(0, repeats=10)
+        print(json.dumps({"lds_read_GBps": round(pk["lds_read_Bps"] / 1e9, 1),
+                          "valu_int32_Tops": round(pk["valu_int32_ops"] / 1e12, 3),
+                          "hbm_copy_GBps": round(pk["hbm_copy_Bps"] / 1e9, 1),
+                          "cus": pk["cus"]}), flush=True)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 "
@@ -337,6 +406,8 @@ def main():
     out = torch.empty((H, W), dtype=torch.int16, device=dev)
     ctx = sm.Stereo(0)
     stream = torch.cuda.current_stream()
+    # the device's peak rates, measured by the library's probes in this run
+    peaks = sm.binding.measure_peaks(0)
 
     nstreams = max(1, args.streams)
     side = [torch.cuda.Stream() for _ in range(nstreams)]  # default priority
@@ -398,7 +469,10 @@ def main():
     X, Y, D = (W + 1) // 2, (H + 1) // 2, (DMAX + 1) // 2
     evals = X * Y * D
     t_match = stage_ms["cost_aggregate_wta"] / 1000.0
-    achieved = OPS_PER_EVAL * evals / t_match
+    lds_bps = LDS_BYTES_PER_EVAL * evals / t_match
+    ops = OPS_PER_EVAL * evals / t_match
+    valu = measured_valu_instructions()
+    lane_ops = valu * 64 / evals if valu else None
     res = {
         "metric": "fps & MDE/s at 1436x992 D=145 vs plain; p50/p99 frame latency",
         "value": round(fps, 2), "unit": "frames/s", "n_gpus": 1, "steps": args.steps,
@@ -412,25 +486,43 @@ def main():
         "mde_per_s": round(W * H * DMAX * fps / 1e6, 1),
         "latency_ms": {"p50": round(percentile(lat, 50), 4), "p99": round(percentile(lat, 99), 4)},
         "stages_ms": {k: round(v, 5) for k, v in stage_ms.items()},
-        "roofline": {"kernel": "k_match", "bound": "alu", "achieved": round(achieved / 1e12, 3),
-                     "peak": round(PEAK_INT_OPS / 1e12, 3), "unit": "Tops/s",
-                     "frac": round(achieved / PEAK_INT_OPS, 4), "traffic": measured_traffic(),
-                     "ops_per_eval": OPS_PER_EVAL, "evals_per_launch": evals,
-                     "avg_launch_ms": round(stage_ms["cost_aggregate_wta"], 5),
-                     "lds": {"bytes_per_eval": LDS_BYTES_PER_EVAL,
-                             "achieved_TBps": round(LDS_BYTES_PER_EVAL * evals / t_match / 1e12, 3),
-                             "peak_TBps": round(PEAK_LDS_BYTES / 1e12, 2),
-                             "frac": round(LDS_BYTES_PER_EVAL * evals / t_match / PEAK_LDS_BYTES, 4)}},
+        "roofline": {
+            "kernel": "k_match", "bound": "lds", "unit": "GB/s",
+            "achieved": round(lds_bps / 1e9, 1), "peak": round(peaks["lds_read_Bps"] / 1e9, 1),
+            "frac": round(lds_bps / peaks["lds_read_Bps"], 4), "traffic": measured_traffic(),
+            "bytes_per_eval": LDS_BYTES_PER_EVAL, "evals_per_launch": evals,
+            "avg_launch_ms": round(stage_ms["cost_aggregate_wta"], 5),
+            "peak_source": "measured in this run: conflict-free ds_read_b128 probe "
+                           "(stereo_calib_lds_read), best of 5 launches",
+            "frac_of_spec": round(lds_bps / SPEC_LDS_BYTES, 4),
+            "alu": {"ops_per_eval_model": OPS_PER_EVAL,
+                    "achieved_Tops": round(ops / 1e12, 3),
+                    "peak_measured_Tops": round(peaks["valu_int32_ops"] / 1e12, 3),
+                    "frac_measured": round(ops / peaks["valu_int32_ops"], 4),
+                    "peak_spec_Tops": round(SPEC_INT_OPS / 1e12, 3),
+                    "executed_lane_ops_per_eval": round(lane_ops, 2) if lane_ops else None,
+                    "executed_frac_measured": (round(lane_ops * evals / t_match /
+                                                     peaks["valu_int32_ops"], 4)
+                                               if lane_ops else None)}},
+        "peaks_measured": {"lds_read_GBps": round(peaks["lds_read_Bps"] / 1e9, 1),
+                           "valu_int32_Tops": round(peaks["valu_int32_ops"] / 1e12, 3),
+                           "hbm_copy_GBps": round(peaks["hbm_copy_Bps"] / 1e9, 1),
+                           "spec": {"lds_GBps": round(SPEC_LDS_BYTES / 1e9, 1),
+                                    "valu_int32_Tops": round(SPEC_INT_OPS / 1e12, 3),
+                                    "hbm_GBps": SPEC_HBM_BYTES / 1e9}},
     }
     ctx.close()
     if args.batch_steps > 0:
         res["batch8"] = batch_leg(sm, args.batch_steps)
     if args.serve_requests > 0:
-        sv = serve_leg(args.serve_requests)
+        pool, ref = serve_pool()
+        sv = serve_leg(args.serve_requests, SERVE_RATE, pool, ref)
         # the served 1436x992 frames (upload and host copy included) against the
         # plain single-frame device latency of the same shape measured above
         sv["p99_1436x992_vs_plain"] = round(
             sv["per_shape"]["1436x992_d145"]["p99_ms"] / res["latency_ms"]["p99"], 3)
+        sv["saturated"] = serve_leg(args.serve_requests // 2, SERVE_RATE_HIGH, pool, ref,
+                                    arrival_seed=601)
         res["serving"] = sv
     if args.soft_steps > 0:
         soft = soft_leg(sm, args.soft_steps)

@@ -277,13 +277,16 @@ int stereo_soft_l1_grad(stereo_ctx* ctx, const float* d_hat, const int16_t* gt,
  * Serving runtime.
  *
  * A persistent worker thread serves frames of mixed shapes as they arrive
- * (the real-time use of the method, Sec. I and Sec. V).  It keeps, per shape
- * and per slot, device buffers, a plan and a HIP graph of the whole path
- * resident; it admits frames in submission order whenever a slot (a stream
- * of its own) is free and the frames in flight, counted by their
- * cost-volume size X*Y*D*4 bytes, stay within mem_budget (a frame alone in
- * flight is always admitted).  Frames in different slots overlap on the
- * device and never share scratch, so each result is bit-identical to
+ * (the real-time use of the method, Sec. I and Sec. V).  It keeps, per shape,
+ * batch size and slot, device buffers, a plan and a HIP graph of the whole
+ * path resident.  Whenever a slot (a stream of its own) is free and the
+ * frames in flight, counted by their cost-volume size X*Y*D*4 bytes, stay
+ * within mem_budget (a frame alone in flight is always admitted), it admits
+ * the oldest pending frame together with the next pending frames of the same
+ * shape that the budget also admits, up to max_batch, rounded down to 1, 2,
+ * 4 or 8 frames, as one batched launch of the path.  Launches in different
+ * slots overlap on the device and never share scratch, and the pairs of a
+ * batch are computed independently, so each result is bit-identical to
  * stereo_disparity's for the same frame.  Times are host steady-clock
  * milliseconds since the server was created.
  * ---------------------------------------------------------------------- */
@@ -292,9 +295,10 @@ typedef struct stereo_server stereo_server; /* opaque */
 typedef struct stereo_server_config {
   uint32_t size;       /* must equal sizeof(stereo_server_config)               */
   int32_t device;      /* HIP device                                            */
-  int32_t slots;       /* frames in flight at most, 1..16, one stream each      */
+  int32_t slots;       /* launches in flight at most, 1..16, one stream each    */
   uint64_t mem_budget; /* admission budget in bytes of X*Y*D*4; 0 = none        */
   stereo_params params;/* method parameters for every frame (flags ignored)     */
+  int32_t max_batch;   /* frames of one shape merged into one launch, 1..8      */
 } stereo_server_config;
 
 typedef struct stereo_server_result {
@@ -304,9 +308,11 @@ typedef struct stereo_server_result {
   double t_submit_ms;  /* stereo_server_submit called                           */
   double t_admit_ms;   /* work enqueued on the slot's stream                    */
   double t_done_ms;    /* output copied to the caller's buffer                  */
+  int32_t batch;       /* frames in the launch that computed it                 */
+  int32_t reserved;    /* 0                                                      */
 } stereo_server_result;
 
-/* 4 slots, no budget, the paper's parameters. */
+/* 4 slots, no budget, batches of up to 8 frames, the paper's parameters. */
 void stereo_server_default_config(stereo_server_config* cfg);
 
 int stereo_server_create(stereo_server** out, const stereo_server_config* cfg);

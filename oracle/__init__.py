@@ -63,6 +63,7 @@ def lib():
             "or_upscale": [P, P, I, I, I, P],
             "or_disparity": [P, P, I, I, I, Dd, Dd, I, I, I, I, I, I, I, I, P] + [P] * 13,
             "or_num_threads": [],
+            "or_set_num_threads": [I],
         }
         for name, args in sig.items():
             f = getattr(L, name)
@@ -253,3 +254,8 @@ def disparity(left, right, dmax, p: Params = Params()):
 
 def num_threads() -> int:
     return lib().or_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """OpenMP threads of the oracle's later calls."""
+    lib().or_set_num_threads(int(n))

@@ -459,3 +459,12 @@ int or_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Threads of the OpenMP loops of later calls (benchmark timing only). */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}

@@ -55,13 +55,14 @@ class SoftParams(ctypes.Structure):
 class ServerConfig(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint32), ("device", ctypes.c_int32),
                 ("slots", ctypes.c_int32), ("mem_budget", ctypes.c_uint64),
-                ("params", Params)]
+                ("params", Params), ("max_batch", ctypes.c_int32)]
 
 
 class ServerResult(ctypes.Structure):
     _fields_ = [("tag", ctypes.c_uint64), ("status", ctypes.c_int32), ("slot", ctypes.c_int32),
                 ("t_submit_ms", ctypes.c_double), ("t_admit_ms", ctypes.c_double),
-                ("t_done_ms", ctypes.c_double)]
+                ("t_done_ms", ctypes.c_double), ("batch", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class StereoError(RuntimeError):
@@ -116,6 +117,12 @@ def lib():
         L.stereo_soft_l1_loss.restype = I
         L.stereo_soft_l1_grad.argtypes = [P, P, P, P, I, I, I, P, P, P]
         L.stereo_soft_l1_grad.restype = I
+        L.stereo_calib_lds_read.argtypes = [P, I, I, P]
+        L.stereo_calib_lds_read.restype = I
+        L.stereo_calib_valu.argtypes = [P, I, I, P]
+        L.stereo_calib_valu.restype = I
+        L.stereo_calib_copy.argtypes = [P, P, U, I, P]
+        L.stereo_calib_copy.restype = I
         L.stereo_server_default_config.argtypes = [ctypes.POINTER(ServerConfig)]
         L.stereo_server_default_config.restype = None
         L.stereo_server_create.argtypes = [ctypes.POINTER(P), ctypes.POINTER(ServerConfig)]
@@ -384,3 +391,46 @@ class Stereo:
         self._raise(rc)
         return g
 
+
+def measure_peaks(device: int = 0, repeats: int = 5) -> dict:
+    """Peak rates of this device from the library's probes
+    (include/stereo_calib.h), each the best of `repeats` timed launches:
+    LDS read bandwidth (bytes/s), 32-bit integer VALU lane operations per
+    second, and device-memory copy bandwidth (bytes read + written per s)."""
+    import torch
+    L = lib()
+    dev = torch.device("cuda", device)
+    props = torch.cuda.get_device_properties(dev)
+    blocks = 8 * props.multi_processor_count
+    sink = torch.empty(blocks * 1024, dtype=torch.int32, device=dev)
+    stream = torch.cuda.current_stream(dev)
+    sh = ctypes.c_void_p(stream.cuda_stream)
+
+    def best(launch, work):
+        launch()  # warm
+        t = []
+        for _ in range(repeats):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            rc = launch()
+            b.record(stream)
+            if rc:
+                raise StereoError(rc, "calibration launch failed")
+            b.synchronize()
+            t.append(a.elapsed_time(b) / 1e3)
+        return work / min(t)
+
+    lds_iters, valu_iters = 400, 400
+    lds = best(lambda: L.stereo_calib_lds_read(sink.data_ptr(), blocks, lds_iters, sh),
+               blocks * 1024 * lds_iters * 256)
+    valu = best(lambda: L.stereo_calib_valu(sink.data_ptr(), blocks, valu_iters, sh),
+                blocks * 1024 * valu_iters * 256)
+    n = 1 << 30
+    src = torch.ones(n // 4, dtype=torch.int32, device=dev)
+    dst = torch.empty_like(src)
+    hbm = best(lambda: L.stereo_calib_copy(src.data_ptr(), dst.data_ptr(), n,
+                                           4 * props.multi_processor_count, sh), 2 * n)
+    del src, dst
+    return {"lds_read_Bps": lds, "valu_int32_ops": valu, "hbm_copy_Bps": hbm,
+            "cus": props.multi_processor_count}

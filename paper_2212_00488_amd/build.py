@@ -8,10 +8,10 @@ import subprocess
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libstereo_mi355x.so")
-SOURCES = [os.path.join(PKG, "csrc", n) for n in ("stereo.hip", "soft.hip", "server.hip")]
+SOURCES = [os.path.join(PKG, "csrc", n) for n in ("stereo.hip", "soft.hip", "server.hip", "calib.hip")]
 HEADERS = [os.path.join(PKG, "csrc", n) for n in ("kernels.hip.h", "soft.hip.h", "context.h", "common.h",
                                                  "pipeline.h")] + [
-    os.path.join(ROOT, "include", "stereo.h")]
+    os.path.join(ROOT, "include", "stereo.h"), os.path.join(ROOT, "include", "stereo_calib.h")]
 
 
 def hipcc_command(out: str = LIB) -> list[str]:

@@ -1,10 +1,12 @@
 // Serving runtime of the integer path: a persistent worker thread takes
 // stereo frames of mixed shapes as they are submitted, keeps per-(shape,
-// slot) device buffers, plans and captured HIP graphs resident, admits
-// frames in arrival order while a slot (a stream of its own) is free and the
-// cost-volume budget of the frames in flight allows, and returns each result
-// with its submit / admit / done times.  Frames in different slots overlap
-// on the device; no two in-flight frames share scratch.
+// batch size, slot) device buffers, plans and captured HIP graphs resident,
+// admits frames in arrival order while a slot (a stream of its own) is free
+// and the cost-volume budget of the frames in flight allows, merging the
+// oldest pending frame with later pending frames of its shape into one
+// batched launch, and returns each result with its submit / admit / done
+// times.  Frames in different slots overlap on the device; no two in-flight
+// launches share scratch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -39,25 +41,29 @@ struct Request {
   Clock::time_point t_submit, t_admit;
 };
 
-// Resident state of one shape on one slot: device inputs and output, pinned
-// staging of the output, the plan and the captured graph of the path.
+// Resident state of one shape and batch size nb on one slot: device inputs
+// and outputs of nb frames, pinned staging of the outputs, the plan and the
+// captured graph of the path over the nb pairs.
 struct Exec {
-  uint8_t* d_left = nullptr;
-  uint8_t* d_right = nullptr;
-  int16_t* d_out = nullptr;
-  int16_t* h_out = nullptr;  // pinned
+  int nb = 1;
+  uint8_t* d_left = nullptr;   // [nb][H][W][3]
+  uint8_t* d_right = nullptr;  // [nb][H][W][3]
+  int16_t* d_out = nullptr;    // [nb][H][W]
+  int16_t* h_out = nullptr;    // pinned [nb][H][W]
   Plan* plan = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
 };
 
+constexpr int kServeMaxBatch = 8;  // frames of one launch (stereo_disparity_batch's pairs)
+
 struct Slot {
   hipStream_t stream = nullptr;
   hipEvent_t done = nullptr;
   bool busy = false;
-  Request req{};
+  std::vector<Request> reqs;  // the frames of the launch in flight
   Exec* ex = nullptr;
-  std::map<std::tuple<int, int, int>, Exec*> execs;
+  std::map<std::tuple<int, int, int, int>, Exec*> execs;  // (W, H, Dmax, nb)
 };
 
 }  // namespace
@@ -74,6 +80,7 @@ struct stereo_server {
   std::deque<stereo_server_result> done; // guarded by mu
   std::deque<Request> pending;           // worker only
   size_t inflight = 0;                   // worker only
+  int max_batch = 1;                     // frames of one shape merged into a launch
   bool stop = false;                     // guarded by mu
   std::string err;                       // guarded by mu (errors of the worker)
   std::thread worker;
@@ -101,35 +108,43 @@ void free_exec(stereo_ctx* c, Exec* e) {
   delete e;
 }
 
-// Builds the resident state of (W, H, Dmax) on slot i: buffers, the slot's
-// plan and a graph captured from the path's launch sequence on its stream.
-int make_exec(stereo_server* s, int i, int W, int H, int Dmax, Exec** out) {
+// Builds the resident state of (W, H, Dmax) for batches of nb frames on
+// slot i: buffers, a plan of its own and a graph captured from the path's
+// launch sequence over the nb pairs on the slot's stream.
+int make_exec(stereo_server* s, int i, int W, int H, int Dmax, int nb, Exec** out) {
   Slot& sl = s->slots[i];
   stereo_ctx* c = s->ctx;
   Exec* e = new Exec();
+  e->nb = nb;
   const size_t img = (size_t)W * H * 3, omap = (size_t)W * H * 2;
-  hipError_t he = hipMalloc(&e->d_left, img);
-  if (he == hipSuccess) he = hipMalloc(&e->d_right, img);
-  if (he == hipSuccess) he = hipMalloc(&e->d_out, omap);
-  if (he == hipSuccess) he = hipHostMalloc(reinterpret_cast<void**>(&e->h_out), omap, hipHostMallocDefault);
+  hipError_t he = hipMalloc(&e->d_left, nb * img);
+  if (he == hipSuccess) he = hipMalloc(&e->d_right, nb * img);
+  if (he == hipSuccess) he = hipMalloc(&e->d_out, nb * omap);
+  if (he == hipSuccess)
+    he = hipHostMalloc(reinterpret_cast<void**>(&e->h_out), nb * omap, hipHostMallocDefault);
   if (he != hipSuccess) {
     (void)hipGetLastError();
     free_exec(c, e);
-    return fail(c, STEREO_ENOMEM, "server buffers for %dx%d: %s", W, H, hipGetErrorString(he));
+    return fail(c, STEREO_ENOMEM, "server buffers for %d x %dx%d: %s", nb, W, H,
+                hipGetErrorString(he));
   }
-  int rc = get_plan(c, W, H, Dmax, s->params, 1, &sl, sl.stream, &e->plan);
+  // the plan's owner key is unique per (slot, batch size): each Exec has its own
+  const void* owner = reinterpret_cast<const char*>(&sl) + nb;
+  int rc = get_plan(c, W, H, Dmax, s->params, nb, owner, sl.stream, &e->plan);
   if (rc) {
     e->plan = nullptr;
     free_exec(c, e);
     return rc;
   }
   stereo_dev::PairPtrs pp{};
-  pp.left[0] = e->d_left;
-  pp.right[0] = e->d_right;
-  pp.out[0] = e->d_out;
+  for (int k = 0; k < nb; ++k) {
+    pp.left[k] = e->d_left + k * img;
+    pp.right[k] = e->d_right + k * img;
+    pp.out[k] = e->d_out + k * (size_t)W * H;
+  }
   he = hipStreamBeginCapture(sl.stream, hipStreamCaptureModeThreadLocal);
   if (he == hipSuccess) {
-    rc = run(c, *e->plan, pp, 1, false, false, sl.stream);
+    rc = run(c, *e->plan, pp, nb, false, false, sl.stream);
     hipError_t ee = hipStreamEndCapture(sl.stream, &e->graph);
     if (!rc && ee != hipSuccess) rc = fail(c, STEREO_EHIP, "capture: %s", hipGetErrorString(ee));
   } else {
@@ -152,11 +167,13 @@ int make_exec(stereo_server* s, int i, int W, int H, int Dmax, Exec** out) {
   return 0;
 }
 
-void post(stereo_server* s, const Request& r, int status, int slot, Clock::time_point t_done) {
+void post(stereo_server* s, const Request& r, int status, int slot, int batch,
+          Clock::time_point t_done) {
   stereo_server_result res{};
   res.tag = r.tag;
   res.status = status;
   res.slot = slot;
+  res.batch = batch;
   res.t_submit_ms = ms_since(s, r.t_submit);
   res.t_admit_ms = status ? res.t_submit_ms : ms_since(s, r.t_admit);
   res.t_done_ms = ms_since(s, t_done);
@@ -167,49 +184,68 @@ void post(stereo_server* s, const Request& r, int status, int slot, Clock::time_
   s->cv_done.notify_all();
 }
 
-// Starts request r on free slot i; returns 0 or an error code (the request
-// is then answered with that status).
-int start(stereo_server* s, int i, Request& r) {
+// Starts the frames of `batch` (one shape, at most kServeMaxBatch) on free
+// slot i as one launch; returns 0 or an error code (the frames are then
+// answered with that status).
+int start(stereo_server* s, int i, std::vector<Request>& batch) {
   Slot& sl = s->slots[i];
-  auto key = std::make_tuple(r.W, r.H, r.Dmax);
+  const Request& r0 = batch.front();
+  const int nb = (int)batch.size();
+  auto key = std::make_tuple(r0.W, r0.H, r0.Dmax, nb);
   auto it = sl.execs.find(key);
   Exec* e = nullptr;
   if (it == sl.execs.end()) {
-    int rc = make_exec(s, i, r.W, r.H, r.Dmax, &e);
-    // out of device memory: free the resident state (graph, buffers, plan) of
-    // other shapes on idle slots, this one first, and try again
+    int rc = make_exec(s, i, r0.W, r0.H, r0.Dmax, nb, &e);
+    // out of device memory: free the resident state (graphs, buffers, plans)
+    // of idle slots, this one first, and try again
     for (int k = 0; rc == STEREO_ENOMEM && k < (int)s->slots.size(); ++k) {
       Slot& q = s->slots[(i + k) % s->slots.size()];
       if (q.busy || q.execs.empty()) continue;
       (void)hipStreamSynchronize(q.stream);
       for (auto& kv : q.execs) free_exec(s->ctx, kv.second);
       q.execs.clear();
-      rc = make_exec(s, i, r.W, r.H, r.Dmax, &e);
+      rc = make_exec(s, i, r0.W, r0.H, r0.Dmax, nb, &e);
     }
     if (rc) return rc;
     sl.execs[key] = e;
   } else {
     e = it->second;
   }
-  const size_t img = (size_t)r.W * r.H * 3, omap = (size_t)r.W * r.H * 2;
-  // a page-locked output buffer takes the map by DMA; pageable memory goes
-  // through the slot's pinned staging and a host copy on completion
-  hipPointerAttribute_t at{};
-  r.direct = hipPointerGetAttributes(&at, r.out) == hipSuccess && at.type == hipMemoryTypeHost;
-  (void)hipGetLastError();  // the query fails for pageable memory; not an error here
-  hipError_t he = hipMemcpyAsync(e->d_left, r.left, img, hipMemcpyHostToDevice, sl.stream);
-  if (he == hipSuccess) he = hipMemcpyAsync(e->d_right, r.right, img, hipMemcpyHostToDevice, sl.stream);
+  const size_t img = (size_t)r0.W * r0.H * 3, omap = (size_t)r0.W * r0.H * 2;
+  hipError_t he = hipSuccess;
+  for (int k = 0; k < nb && he == hipSuccess; ++k) {
+    he = hipMemcpyAsync(e->d_left + k * img, batch[k].left, img, hipMemcpyHostToDevice, sl.stream);
+    if (he == hipSuccess)
+      he = hipMemcpyAsync(e->d_right + k * img, batch[k].right, img, hipMemcpyHostToDevice,
+                          sl.stream);
+  }
   if (he == hipSuccess) he = hipGraphLaunch(e->exec, sl.stream);
-  if (he == hipSuccess)
-    he = hipMemcpyAsync(r.direct ? (void*)r.out : (void*)e->h_out, e->d_out, omap,
-                        hipMemcpyDeviceToHost, sl.stream);
+  // a page-locked output buffer takes its map by DMA; pageable memory goes
+  // through the slot's pinned staging and a host copy on completion
+  for (int k = 0; k < nb && he == hipSuccess; ++k) {
+    Request& r = batch[k];
+    hipPointerAttribute_t at{};
+    r.direct = hipPointerGetAttributes(&at, r.out) == hipSuccess && at.type == hipMemoryTypeHost;
+    (void)hipGetLastError();  // the query fails for pageable memory; not an error here
+    he = hipMemcpyAsync(r.direct ? (void*)r.out : (void*)(e->h_out + k * (size_t)r.W * r.H),
+                        e->d_out + k * (size_t)r.W * r.H, omap, hipMemcpyDeviceToHost, sl.stream);
+  }
   if (he == hipSuccess) he = hipEventRecord(sl.done, sl.stream);
   if (he != hipSuccess) return fail(s->ctx, STEREO_EHIP, "enqueue: %s", hipGetErrorString(he));
-  r.t_admit = Clock::now();
+  const Clock::time_point now = Clock::now();
+  for (Request& r : batch) r.t_admit = now;
   sl.busy = true;
-  sl.req = r;
+  sl.reqs = batch;
   sl.ex = e;
   return 0;
+}
+
+// Largest power of two <= n (batch sizes 1, 2, 4, 8 keep the resident graphs
+// per shape and slot few).
+int pow2_floor(int n) {
+  int b = 1;
+  while (2 * b <= n) b *= 2;
+  return b;
 }
 
 void worker_main(stereo_server* s) {
@@ -241,34 +277,59 @@ void worker_main(stereo_server* s) {
         status = STEREO_EHIP;
         std::lock_guard<std::mutex> g(s->mu);
         s->err = hipGetErrorString(q);
-      } else if (!sl.req.direct) {
-        std::memcpy(sl.req.out, sl.ex->h_out, (size_t)sl.req.W * sl.req.H * 2);
+      }
+      const Clock::time_point now = Clock::now();
+      const int nb = (int)sl.reqs.size();
+      for (int k = 0; k < nb; ++k) {
+        const Request& r = sl.reqs[k];
+        const size_t px = (size_t)r.W * r.H;
+        if (!status && !r.direct) std::memcpy(r.out, sl.ex->h_out + k * px, px * 2);
+        s->inflight -= r.volume;
+        post(s, r, status, i, nb, now);
       }
       sl.busy = false;
-      s->inflight -= sl.req.volume;
-      post(s, sl.req, status, i, Clock::now());
+      sl.reqs.clear();
       progressed = true;
     }
-    // admission in arrival order: a free slot and room in the budget (a
-    // frame alone in flight is always admitted)
+    // admission in arrival order: the oldest pending frame goes to a free
+    // slot when the budget has room (a frame alone in flight is always
+    // admitted), together with the next pending frames of its shape that the
+    // budget also admits, up to max_batch, as one batched launch
     while (!s->pending.empty()) {
-      Request& r = s->pending.front();
+      const Request& head = s->pending.front();
       int free_slot = -1;
       for (int i = 0; i < (int)s->slots.size() && free_slot < 0; ++i)
         if (!s->slots[i].busy) free_slot = i;
       if (free_slot < 0) break;
-      if (s->cfg.mem_budget && s->inflight > 0 && s->inflight + r.volume > s->cfg.mem_budget) break;
-      int rc = start(s, free_slot, r);
+      const uint64_t budget = s->cfg.mem_budget;
+      if (budget && s->inflight > 0 && s->inflight + head.volume > budget) break;
+      std::vector<size_t> pick{0};
+      size_t vol = head.volume;
+      for (size_t k = 1; k < s->pending.size() && (int)pick.size() < s->max_batch; ++k) {
+        const Request& r = s->pending[k];
+        if (r.W != head.W || r.H != head.H || r.Dmax != head.Dmax) continue;
+        if (budget && s->inflight + vol + r.volume > budget) break;
+        pick.push_back(k);
+        vol += r.volume;
+      }
+      pick.resize(pow2_floor((int)pick.size()));
+      std::vector<Request> batch;
+      vol = 0;
+      for (size_t k : pick) {
+        batch.push_back(s->pending[k]);
+        vol += s->pending[k].volume;
+      }
+      for (size_t n = pick.size(); n-- > 0;) s->pending.erase(s->pending.begin() + pick[n]);
+      int rc = start(s, free_slot, batch);
       if (rc) {
         {
           std::lock_guard<std::mutex> g(s->mu);
           s->err = s->ctx->err;
         }
-        post(s, r, rc, -1, Clock::now());
+        for (const Request& r : batch) post(s, r, rc, -1, (int)batch.size(), Clock::now());
       } else {
-        s->inflight += r.volume;
+        s->inflight += vol;
       }
-      s->pending.pop_front();
       progressed = true;
     }
     if (!progressed) std::this_thread::sleep_for(std::chrono::microseconds(20));
@@ -287,12 +348,14 @@ void stereo_server_default_config(stereo_server_config* cfg) {
   cfg->slots = 4;
   cfg->mem_budget = 0;
   stereo_default_params(&cfg->params);
+  cfg->max_batch = kServeMaxBatch;
 }
 
 int stereo_server_create(stereo_server** out, const stereo_server_config* cfg) {
   if (!out || !cfg) return STEREO_EINVAL;
   *out = nullptr;
-  if (cfg->size != sizeof(stereo_server_config) || cfg->slots < 1 || cfg->slots > 16)
+  if (cfg->size != sizeof(stereo_server_config) || cfg->slots < 1 || cfg->slots > 16 ||
+      cfg->max_batch < 1 || cfg->max_batch > kServeMaxBatch)
     return STEREO_EINVAL;
   stereo_ctx* c = nullptr;
   int rc = stereo_create(&c, cfg->device, 0);
@@ -305,6 +368,7 @@ int stereo_server_create(stereo_server** out, const stereo_server_config* cfg) {
   }
   stereo_server* s = new stereo_server();
   s->cfg = *cfg;
+  s->max_batch = cfg->max_batch;
   s->params = p;
   s->params.flags = 0;
   s->ctx = c;

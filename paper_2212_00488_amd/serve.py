@@ -20,10 +20,12 @@ from .binding import ServerConfig, ServerResult, StereoError, lib
 class Server:
     """A serving runtime on one HIP device."""
 
-    def __init__(self, device: int = 0, slots: int = 4, mem_budget: int = 0, params=None):
+    def __init__(self, device: int = 0, slots: int = 4, mem_budget: int = 0, params=None,
+                 max_batch: int = 8):
         cfg = ServerConfig()
         lib().stereo_server_default_config(ctypes.byref(cfg))
         cfg.device, cfg.slots, cfg.mem_budget = device, slots, mem_budget
+        cfg.max_batch = max_batch
         if params is not None:
             cfg.params = params
         h = ctypes.c_void_p()
@@ -59,7 +61,7 @@ class Server:
             r = buf[i]
             out.append(dict(tag=int(r.tag), status=int(r.status), slot=int(r.slot),
                             t_submit_ms=r.t_submit_ms, t_admit_ms=r.t_admit_ms,
-                            t_done_ms=r.t_done_ms))
+                            t_done_ms=r.t_done_ms, batch=int(r.batch)))
             self._keep.pop(int(r.tag), None)
         return out
 

@@ -26,7 +26,8 @@ def test_header_declares_the_boundary():
     names = declared_functions()
     for n in ("stereo_create", "stereo_disparity", "stereo_destroy", "stereo_default_params",
               "stereo_disparity_batch", "stereo_get_intermediate", "stereo_last_error",
-              "stereo_disparity_noalloc"):
+              "stereo_disparity_noalloc", "stereo_calib_lds_read", "stereo_calib_valu",
+              "stereo_calib_copy"):
         assert n in names
 
 

@@ -46,10 +46,12 @@ def make_stream(n, seed, rate):
     return kinds, which, arrivals
 
 
-def run_stream(pool, n, seed, rate, slots, budget=0, pinned=False):
+def run_stream(pool, n, seed, rate, slots, budget=0, pinned=False, max_batch=8, kinds_from=None):
     frames, ref = pool
     kinds, which, arrivals = make_stream(n, seed, rate)
-    srv = Server(0, slots=slots, mem_budget=budget)
+    if kinds_from is not None:
+        kinds = np.asarray(kinds_from)[kinds % len(kinds_from)]
+    srv = Server(0, slots=slots, mem_budget=budget, max_batch=max_batch)
     try:
         fr = [(frames[k][j].left, frames[k][j].right) for k, j in zip(kinds, which)]
         dm = [SHAPES[k][2] for k in kinds]
@@ -84,7 +86,7 @@ def test_burst_of_mixed_frames_matches_alone(pool):
 
 
 def test_poisson_stream_single_slot_matches_alone(pool):
-    rep, _ = run_stream(pool, 24, seed=601, rate=400.0, slots=1)
+    rep, _ = run_stream(pool, 24, seed=601, rate=400.0, slots=1, max_batch=1)
     assert {r["slot"] for r in rep.results} == {0}
     # one slot: frames run one after the other in submission order
     res = sorted(rep.results, key=lambda r: r["t_admit_ms"])
@@ -120,3 +122,34 @@ def test_served_maps_equal_stereo_disparity(pool):
             assert np.array_equal(out.cpu().numpy(), ref[(k, 0)]), SHAPES[k]
     finally:
         ctx.close()
+
+
+def test_same_shape_frames_are_batched(pool):
+    """A burst of frames of two shapes on two slots: pending frames of the
+    head's shape join its launch (1, 2, 4 or 8 frames), every map still
+    equals the oracle's, and the frames of one launch share shape, slot and
+    admission time."""
+    rep, kinds = run_stream(pool, 40, seed=604, rate=None, slots=2, kinds_from=[1, 4])
+    res = rep.results
+    sizes = {r["batch"] for r in res}
+    assert sizes <= {1, 2, 4, 8} and max(sizes) > 1, sizes
+    launches = {}
+    for r in res:
+        launches.setdefault((r["slot"], r["t_admit_ms"]), []).append(r)
+    for group in launches.values():
+        assert len(group) == group[0]["batch"]
+        assert len({SHAPES[kinds[r["tag"]]] for r in group}) == 1
+
+
+def test_budget_holds_with_batches(pool):
+    """Batches count every frame against the budget: at most two paper-sized
+    frames in flight, whatever the batching."""
+    budget = 2 * volume(4)
+    rep, kinds = run_stream(pool, 24, seed=605, rate=None, slots=4, budget=budget,
+                            kinds_from=[4])
+    res = rep.results
+    assert max(r["batch"] for r in res) <= 2
+    for r in res:
+        t = r["t_admit_ms"]
+        live = [q for q in res if q["t_admit_ms"] <= t < q["t_done_ms"]]
+        assert sum(volume(kinds[q["tag"]]) for q in live) <= budget
