@@ -588,13 +588,17 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
         s_plane[(r + i + 1) * 64 + lane] = run;
       }
     };
+    // The next batch is loaded unconditionally (past the segment end it
+    // reloads the last row): with the loads behind a branch, the waits at the
+    // join must hold for the path with them in flight and the path without,
+    // and the compiler then waited for the next batch too.
     RowIn in0[kRowBatch], in1[kRowBatch];  // two buffer sets, used in turn
     if (r0 < r1) load_batch(r0, in0);
     for (int r = r0; r < r1; r += 2 * kRowBatch) {
-      if (r + kRowBatch < r1) load_batch(r + kRowBatch, in1);
+      load_batch(r + kRowBatch, in1);
       process_batch(r, in0);
       if (r + kRowBatch >= r1) break;
-      if (r + 2 * kRowBatch < r1) load_batch(r + 2 * kRowBatch, in0);
+      load_batch(r + 2 * kRowBatch, in0);
       process_batch(r + kRowBatch, in1);
     }
     s_seg[wave][c] = run;

@@ -17,7 +17,7 @@ using namespace stereo_dev;
 namespace stereo_host {
 
 constexpr int kSoftMaxPairs = 64;
-constexpr size_t kSlabBudget = size_t(512) << 20;  // dL/dCA (then t) + dL/dCA_x planes of a slab
+constexpr size_t kSlabBudget = size_t(512) << 20;  // dL/dCA + dL/dCA_x planes of a slab
 
 struct SoftPlan {
   int n = 0, W = 0, H = 0, Dmax = 0, X = 0, Y = 0, D = 0;
@@ -40,7 +40,9 @@ struct SoftPlan {
   float2* part = nullptr;      // [n][nchunk][Y][X]
   float4* pc = nullptr;        // [n][Y][X]
   float* gca = nullptr;        // [nds][n][Y][X]
-  float* gcax = nullptr;       // [nds][n][Y][X] dL/dCA_x (the gca planes then hold t)
+  float* gcax = nullptr;       // [nds][n][Y][X] dL/dCA_x
+  float* gr_part = nullptr;    // [n][nstrips][Y][WP] right-gradient partials of a slab
+  int WP = 0;                  // 64 + nds - 1 columns per partial row
   float* g_half = nullptr;     // [2n][Y][X]
   float2* lam_part = nullptr;  // [lam_count]
   uint64_t last_use = 0;
@@ -123,11 +125,14 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
   pl->csize = best_chunk_size(groups, D, pl->rows, c->num_cu);
   pl->nchunk = (D + pl->csize - 1) / pl->csize;
   const size_t npix = (size_t)X * Y;
+  // at most 128 disparities per slab (k_soft_tr's LDS rows of right gradients)
   pl->nds = p.slab > 0 ? std::min(p.slab, D)
                        : (int)std::max<size_t>(1, std::min<size_t>(D, kSlabBudget / (2 * n * npix * 4)));
+  pl->nds = std::min(pl->nds, kTrMaxWP - 63);
+  pl->WP = 64 + pl->nds - 1;
   pl->nbands_tr = (Y + kSoftBR - 1) / kSoftBR;
   const int nslab = (D + pl->nds - 1) / pl->nds;
-  pl->lam_count = (size_t)nslab * pl->nds * n * pl->nstrips * pl->nbands_tr;
+  pl->lam_count = (size_t)nslab * n * pl->nstrips * pl->nbands_tr;
 
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   const size_t nimg = 2 * (size_t)n;
@@ -142,7 +147,7 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
                  al(nimg * Y * pl->XA * 4) + al(nimg * Y * pl->XS * 8) + al(n * npix * 4) +
                  al((size_t)n * pl->nchunk * npix * 8) + al(n * npix * 16) +
                  2 * al((size_t)pl->nds * n * npix * 4) + al(nimg * npix * 4) +
-                 al(pl->lam_count * 8);
+                 al(pl->lam_count * 8) + al((size_t)n * pl->nstrips * Y * pl->WP * 4);
   if (c->mem_cap && c->used + bytes > c->mem_cap) {
     delete pl;
     return fail(c, STEREO_ENOMEM, "soft plan needs %zu bytes, cap %zu, in use %zu", bytes,
@@ -168,6 +173,7 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
   pl->gcax = carve<float>(cur, (size_t)pl->nds * n * npix);
   pl->g_half = carve<float>(cur, nimg * npix);
   pl->lam_part = carve<float2>(cur, pl->lam_count);
+  pl->gr_part = carve<float>(cur, (size_t)n * pl->nstrips * Y * pl->WP);
   // zero padding of the arm and pixel planes (kernels write the image part),
   // ordered on the plan's stream: no other stream is stalled
   hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, s, reinterpret_cast<float*>(pl->arms),
@@ -369,16 +375,17 @@ int stereo_soft_backward(stereo_ctx* c, const float* left, const float* right, i
                        dim3(256), 0, stream, pl->gca, pl->arms, X, Y, pl->XA, pl->p.arm_y, pl->n,
                        pl->gcax);
     TrArgs ta{};
-    ta.gcax = pl->gcax; ta.arms = pl->arms; ta.sp = pl->sp; ta.lam = lambdas; ta.t = pl->gca;
+    ta.gcax = pl->gcax; ta.arms = pl->arms; ta.sp = pl->sp; ta.lam = lambdas;
+    ta.g_half = pl->g_half; ta.gr_part = pl->gr_part;
     ta.lam_part = pl->lam_part + lam_off;
     ta.X = X; ta.Y = Y; ta.XS = pl->XS; ta.pads = pl->pads; ta.XA = pl->XA;
-    ta.npair = pl->n; ta.dlo = dlo;
+    ta.npair = pl->n; ta.dlo = dlo; ta.dhi = dhi; ta.WP = pl->WP;
     ta.nstrips = pl->nstrips; ta.nbands = pl->nbands_tr;
-    dim3 tg((unsigned)(pl->nstrips * pl->nbands_tr), (unsigned)nds, (unsigned)pl->n);
+    dim3 tg((unsigned)(pl->nstrips * pl->nbands_tr), (unsigned)pl->n);
     hipLaunchKernelGGL(k_soft_tr, tg, dim3(256), 0, stream, ta);
-    lam_off += (size_t)tg.x * tg.y * tg.z;
-    hipLaunchKernelGGL(k_soft_gimg, dim3((X + 255) / 256, Y, pl->n), dim3(256), 0, stream,
-                       pl->gca, nds, dlo, pl->n, X, Y, pl->g_half);
+    lam_off += (size_t)tg.x * tg.y;
+    hipLaunchKernelGGL(k_soft_gright, dim3((X + 255) / 256, Y, pl->n), dim3(256), 0, stream,
+                       pl->gr_part, pl->nstrips, pl->WP, dlo, dhi, X, Y, pl->g_half);
   }
   hipLaunchKernelGGL(k_soft_gfull, dim3((W + 255) / 256, H, 2 * pl->n), dim3(256), 0, stream,
                      pl->g_half, W, H, X, Y, g_left, g_right);

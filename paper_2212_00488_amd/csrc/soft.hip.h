@@ -21,8 +21,9 @@
 //             k_soft_tcol   transposed vertical window sums (difference
 //                           arrays in an LDS ring, one pass down each column)
 //             k_soft_tr     transposed horizontal window sums back to dL/dC,
-//                           then dC/d(dI), dC/d(lambda) per pixel
-//             k_soft_gimg   dL/d(half image) of both images over the slab
+//                           then dC/d(dI), dC/d(lambda) per pixel, summed over
+//                           the slab into the half-image gradients
+//             k_soft_gright dL/d(right half image) from the strips' partials
 //             k_soft_gfull  transposed downscale and gray: dL/d(RGB)
 //             k_soft_lam    fixed-order sum of the lambda partials
 //   loss      k_l1_*        mean |2 d_hat - GT(2x,2y)| over non-occluded
@@ -316,10 +317,10 @@ __global__ void __launch_bounds__(kThreads) k_soft_agg(SoftArgs a) {
     RowIn in0[2], in1[2];  // two buffer sets, used in turn
     if (r0 < r1) load_batch(r0, in0);
     for (int r = r0; r < r1; r += 4) {
-      if (r + 2 < r1) load_batch(r + 2, in1);
+      load_batch(r + 2, in1);  // unconditional: see k_match's row pass
       process_batch(r, in0);
       if (r + 2 >= r1) break;
-      if (r + 4 < r1) load_batch(r + 4, in0);
+      load_batch(r + 4, in0);
       process_batch(r + 2, in1);
     }
     s_seg[wave][c] = run;
@@ -533,133 +534,202 @@ __global__ void __launch_bounds__(256) k_soft_tcol(const float* __restrict__ gca
 
 // ------------------------------------------------------------- k_soft_tr
 // Transpose of the horizontal window sum (Eq. 7) over a 64-column strip and
-// a band of kSoftBR rows for one disparity, then the cost derivatives there.
+// a band of kSoftBR rows, for every disparity of a slab in turn, then the
+// cost derivatives there, summed over the slab into the half-image gradients.
 //   CA_x(x,y) = sum_{t=-m}^{n} C(x+t,y) transposes to a difference array
 //   along the row (+g at x - m, -g at x + n + 1) and a prefix along it,
 //   giving dL/dC from dL/dCA_x (k_soft_tcol's planes).
 // Then with dI = L(x,y) - R(x-d,y), a = 255 |dI|, E = e^{-a/lambda_AD}:
 //   t = dL/dC * dC/d(dI) = dL/dC * (255 / lambda_AD) E sign(dI)
+//   dL/dL(x,y)        += t       dL/dR(x-d,y) -= t
 //   dL/dlambda_AD     += dL/dC * (-E a / lambda_AD^2)
 //   dL/dlambda_census += dL/dC * (-e^{-H/lambda_census} H / lambda_census^2)
 // for x - d >= 0 (the constant cost of x - d < 0 has no derivative).
 // The sources of a row are the columns x0 - 32 .. x0 + 95 (every column
-// whose horizontal window reaches the strip, arm_x <= 31): the 16 lanes of
-// a DPP row take 8 consecutive source columns each of one band row.  The
-// difference arrays are integer fixed point with a per-row scale (as in
-// k_soft_tcol: terms below 2^23, sums of at most 63 terms below 2^29), added
-// with LDS integer atomics, so the result does not depend on their order.
-// grid: (strips * bands, nds, n), block 256.
+// whose horizontal window reaches the strip, arm_x <= 31).  Wave w owns the
+// band rows w, w + 4, w + 8, w + 12 entirely: lane l loads source columns
+// x0 - 32 + l and x0 + 32 + l of them (coalesced), scatters them into the
+// rows' difference arrays, scans the rows and takes the derivatives at
+// output column x0 + l, so the disparity loop needs no barrier (a wave's LDS
+// accesses are served in order).  The difference arrays are integer fixed
+// point with a per-row scale (as in k_soft_tcol: terms below 2^23, sums of
+// at most 63 terms below 2^29), added with LDS integer atomics, so the
+// result does not depend on their order.  The left gradient of a pixel stays
+// in a register over the slab and is added to g_half once; the right one, at
+// column x - d, goes to the wave's LDS row (one writer per entry and
+// disparity, disparities in order) and then to this strip's partial row,
+// which k_soft_gright sums over the strips.  The horizontal arms and the
+// left pixels do not depend on d and are loaded once.
+// grid: (strips * bands, n), block 256.
 struct TrArgs {
   const float* gcax;        // [nds][n][Y][X] dL/dCA_x
   const uint32_t* arms;     // [2n][Y][XA]
   const uint2* sp;          // [2n][Y][XS] padded pixel planes
   const float* lam;         // device [2]
-  float* t;                 // [nds][n][Y][X]
+  float* g_half;            // [2n][Y][X] half-image gradients (left ones added here)
+  float* gr_part;           // [n][strips][Y][WP] -dL/dR partials of this slab
   float2* lam_part;         // one {d/dlambda_AD, d/dlambda_census} per workgroup
-  int X, Y, XS, pads, XA, npair, dlo, nstrips, nbands;
+  int X, Y, XS, pads, XA, npair, dlo, dhi, nstrips, nbands, WP;
 };
 
-// Maximum over the 16 lanes of each DPP row (every lane receives it).
-__device__ __forceinline__ float row16_max(float v) {
+// Maximum over the 64 lanes of a wave, in every lane.
+__device__ __forceinline__ float wave_max_f(float v) {
   v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false)));  // row_ror:8
   v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false)));  // row_ror:4
   v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4e, 0xf, 0xf, false)));   // quad_perm 2,3,0,1
   v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xb1, 0xf, 0xf, false)));   // quad_perm 1,0,3,2
-  return v;
+  const float a = fmaxf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)),
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16)));
+  const float b = fmaxf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32)),
+                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48)));
+  return fmaxf(a, b);
 }
+
+constexpr int kTrMaxWP = 64 + 127;  // 64 columns + a slab of up to 128 disparities
 
 __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
   constexpr int BR = kSoftBR;
-  static_assert(BR == 16, "one band row per 16 threads");
-  __shared__ int s_d[BR][65];
-  __shared__ float s_down[BR];
+  static_assert(BR == 16, "four band rows per wave");
+  constexpr int RPW = BR / 4;  // rows per wave: r = wave + 4 i
+  __shared__ int s_d[BR][64];
+  __shared__ float s_gr[BR][kTrMaxWP];
   __shared__ float2 s_red[4];
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int strip = blockIdx.x % a.nstrips, band = blockIdx.x / a.nstrips;
-  const int dj = blockIdx.y, d = a.dlo + dj, pair = blockIdx.z;
+  const int pair = blockIdx.y;
   const int X = a.X, Y = a.Y;
   const int x0 = strip * 64, y0 = band * BR;
   const size_t plane = (size_t)X * Y;
-  const float* g = a.gcax + ((size_t)dj * a.npair + pair) * plane;
   const uint32_t* arm = a.arms + (size_t)(2 * pair) * Y * a.XA;
-  // source columns x0 - 32 + 8 j .. + 7 (j = t & 15) of band row t >> 4
-  const int sr = t >> 4, sj = t & 15, sy = y0 + sr;
-  const bool yin = sy < Y;
-  const int ysafe = min(sy, Y - 1);
-  float gv[8];
-  uint32_t mv[8];
+  const uint2* spl = a.sp + (size_t)(2 * pair) * Y * a.XS + a.pads;
+  const uint2* spr = a.sp + (size_t)(2 * pair + 1) * Y * a.XS + a.pads;
+  const int x = x0 + lane;
+  const bool xin = x < X;
+  // per row i and source h: column x0 - 32 + 64 h + lane
+  int ys[RPW];
+  bool yv[RPW], cv[RPW][2];
+  uint32_t mv[RPW][2];
+  uint2 pl_[RPW];
+  float gl[RPW];
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const int col = x0 - 32 + 8 * sj + k;
-    const bool cv = yin && col >= 0 && col < X;
-    const int cc = min(max(col, 0), X - 1);
-    const float v = g[(size_t)ysafe * X + cc];
-    const uint32_t m = arm[(size_t)ysafe * a.XA + cc];
-    gv[k] = cv ? v : 0.f;
-    mv[k] = m;
-  }
-  for (int i = t; i < BR * 65; i += 256) (&s_d[0][0])[i] = 0;
-  float mx = 0.f;
+  for (int i = 0; i < RPW; ++i) {
+    const int y = y0 + wave + 4 * i;
+    yv[i] = y < Y;
+    ys[i] = min(y, Y - 1);
 #pragma unroll
-  for (int k = 0; k < 8; ++k) mx = fmaxf(mx, fabsf(gv[k]));
-  mx = row16_max(mx);
-  int e = 0;
-  (void)frexpf(mx, &e);
-  const float up = mx > 0.f ? ldexpf(1.f, 23 - e) : 0.f;
-  if (sj == 0) s_down[sr] = mx > 0.f ? ldexpf(1.f, e - 23) : 0.f;
-  __syncthreads();
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    if (gv[k] != 0.f) {
-      const int q = (int)rintf(gv[k] * up);
-      const int col = x0 - 32 + 8 * sj + k;
-      const int lo = col - (int)(mv[k] & 255u) - x0, hi = col + (int)((mv[k] >> 8) & 255u) + 1 - x0;
-      if (hi > 0 && lo < 64) {
-        atomicAdd(&s_d[sr][max(lo, 0)], q);
-        if (hi < 64) atomicAdd(&s_d[sr][hi], -q);
-      }
+    for (int h = 0; h < 2; ++h) {
+      const int col = x0 - 32 + 64 * h + lane;
+      cv[i][h] = yv[i] && col >= 0 && col < X;
+      mv[i][h] = arm[(size_t)ys[i] * a.XA + min(max(col, 0), X - 1)];
     }
+    pl_[i] = xin ? spl[(size_t)ys[i] * a.XS + x] : make_uint2(0u, 0u);
+    gl[i] = 0.f;
+    for (int c = lane; c < kTrMaxWP; c += 64) s_gr[wave + 4 * i][c] = 0.f;
   }
-  // operands of the cost derivative at the rows r = wave + 4 i of this wave
   const float lam_ad = a.lam[0], lam_c = a.lam[1];
   const float k2 = 255.f * 1.4426950408889634f / lam_ad;
   const float kt = 255.f / lam_ad, ka = 1.f / (lam_ad * lam_ad), kc = 1.f / (lam_c * lam_c);
   const float l2c = 1.4426950408889634f / lam_c;
   float pa = 0.f, pcs = 0.f;
-  const uint2* spl = a.sp + (size_t)(2 * pair) * Y * a.XS + a.pads;
-  const uint2* spr = a.sp + (size_t)(2 * pair + 1) * Y * a.XS + a.pads;
-  float* tout = a.t + ((size_t)dj * a.npair + pair) * plane;
-  constexpr int RPW = BR / 4;  // rows per wave
-  uint2 pl_[RPW], pr_[RPW];
-  const int x = x0 + lane;
-  const bool xin = x < X, dv = x - d >= 0;
+  // the loads of disparity d + 1 are issued before d is processed (two
+  // register sets used in turn; the last disparity is reloaded past the end,
+  // so the loads are unconditional and the waits stay exact)
+  struct DIn {
+    float g[RPW][2];
+    uint2 pr[RPW];
+  };
+  const float* gbase = a.gcax + (size_t)pair * plane;
+  const size_t dstride = (size_t)a.npair * plane;
+  auto load_d = [&](int d, DIn& in) {
+    const float* g = gbase + (size_t)(d - a.dlo) * dstride;
+    const bool dv = x - d >= 0;
 #pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int y = min(y0 + wave + 4 * i, Y - 1);
-    pl_[i] = xin ? spl[(size_t)y * a.XS + x] : make_uint2(0u, 0u);
-    pr_[i] = (xin && dv) ? spr[(size_t)y * a.XS + x - d] : make_uint2(0u, 0u);
-  }
-  __syncthreads();
-  // prefix along each row, then the cost derivatives
+    for (int i = 0; i < RPW; ++i) {
 #pragma unroll
-  for (int i = 0; i < RPW; ++i) {
-    const int r = wave + 4 * i, y = y0 + r;
-    if (y >= Y) break;
-    const float gc = (float)(int)wave_scan_incl((uint32_t)s_d[r][lane]) * s_down[r];
-    if (xin) {
-      float tv = 0.f;
-      if (dv) {
-        const float di = __uint_as_float(pl_[i].x) - __uint_as_float(pr_[i].x);
+      for (int h = 0; h < 2; ++h) {
+        const int cc = min(max(x0 - 32 + 64 * h + lane, 0), X - 1);
+        in.g[i][h] = g[ys[i] * X + cc];
+      }
+      in.pr[i] = spr[ys[i] * a.XS + min(max(x - d, 0), X - 1)];
+      if (!(xin && dv)) in.pr[i] = make_uint2(0u, 0u);
+    }
+  };
+  auto process_d = [&](int d, const DIn& in) {
+    const bool dv = x - d >= 0;
+    // the wave's LDS accesses stay in program order across lanes: the
+    // compiler may not move one across these points
+    WAVE_LDS_ORDER();
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) s_d[wave + 4 * i][lane] = 0;
+    WAVE_LDS_ORDER();
+    float down[RPW];
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const float g0 = cv[i][0] ? in.g[i][0] : 0.f, g1 = cv[i][1] ? in.g[i][1] : 0.f;
+      const float mx = wave_max_f(fmaxf(fabsf(g0), fabsf(g1)));
+      int e = 0;
+      (void)frexpf(mx, &e);
+      const float up = mx > 0.f ? ldexpf(1.f, 23 - e) : 0.f;
+      down[i] = mx > 0.f ? ldexpf(1.f, e - 23) : 0.f;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const float gvh = h ? g1 : g0;
+        if (gvh != 0.f) {
+          const int q = (int)rintf(gvh * up);
+          const int col = x0 - 32 + 64 * h + lane;
+          const int lo = col - (int)(mv[i][h] & 255u) - x0;
+          const int hi = col + (int)((mv[i][h] >> 8) & 255u) + 1 - x0;
+          if (hi > 0 && lo < 64) {
+            atomicAdd(&s_d[wave + 4 * i][max(lo, 0)], q);
+            if (hi < 64) atomicAdd(&s_d[wave + 4 * i][hi], -q);
+          }
+        }
+      }
+    }
+    WAVE_LDS_ORDER();
+    // prefix along each row, then the cost derivatives; the right gradient
+    // of column x - d sits at s_gr[r][x - d - (x0 - dhi + 1)]
+    const int gcol = lane + (a.dhi - 1 - d);
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) {
+      const int r = wave + 4 * i;
+      const float gc = (float)(int)wave_scan_incl((uint32_t)s_d[r][lane]) * down[i];
+      if (xin && dv && yv[i]) {
+        const float di = __uint_as_float(pl_[i].x) - __uint_as_float(in.pr[i].x);
         const float ad = fabsf(di);
         const float E = fast_exp2(-ad * k2);
         const float sg = di > 0.f ? 1.f : (di < 0.f ? -1.f : 0.f);
-        tv = gc * kt * E * sg;
+        const float tv = gc * kt * E * sg;
+        gl[i] += tv;
+        s_gr[r][gcol] -= tv;
         pa += gc * (-E * 255.f * ad * ka);
-        const int hh = __builtin_popcount(pl_[i].y ^ pr_[i].y);
+        const int hh = __builtin_popcount(pl_[i].y ^ in.pr[i].y);
         pcs += gc * (-fast_exp2(-(float)hh * l2c) * (float)hh * kc);
       }
-      tout[(size_t)y * X + x] = tv;
     }
+    WAVE_LDS_ORDER();
+  };
+  DIn in0, in1;
+  load_d(a.dlo, in0);
+  for (int d = a.dlo; d < a.dhi; d += 2) {
+    load_d(min(d + 1, a.dhi - 1), in1);
+    process_d(d, in0);
+    if (d + 1 >= a.dhi) break;
+    load_d(min(d + 2, a.dhi - 1), in0);
+    process_d(d + 1, in1);
+  }
+  WAVE_LDS_ORDER();
+  // left gradients: each pixel has one owner; slabs run one after another
+  float* glp = a.g_half + (size_t)(2 * pair) * plane;
+  // right partials of this strip: columns x0 - dhi + 1 .. x0 + 63 - dlo
+  const int wd = 64 + (a.dhi - a.dlo) - 1;
+  float* gp = a.gr_part + ((size_t)pair * a.nstrips + strip) * Y * a.WP;
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+    if (!yv[i]) continue;
+    const int y = ys[i], r = wave + 4 * i;
+    if (xin) glp[(size_t)y * X + x] += gl[i];
+    for (int c = lane; c < wd; c += 64) gp[(size_t)y * a.WP + c] = s_gr[r][c];
   }
   // fixed-order reduction of the lambda partials over the workgroup
 #pragma unroll
@@ -672,45 +742,27 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
   if (t == 0) {
     float2 s = s_red[0];
     for (int w = 1; w < 4; ++w) { s.x += s_red[w].x; s.y += s_red[w].y; }
-    a.lam_part[((size_t)pair * gridDim.y + dj) * gridDim.x + blockIdx.x] = s;
+    a.lam_part[(size_t)pair * gridDim.x + blockIdx.x] = s;
   }
 }
 
-// ----------------------------------------------------------- k_soft_gimg
-// dL/d(half image) accumulated over a slab of disparities d = dlo + j:
-//   left  (x,y) += sum_j t_j(x, y)
-//   right (x,y) -= sum_j t_j(x + d_j, y)   (x + d_j < X)
+// --------------------------------------------------------- k_soft_gright
+// dL/dR(x,y) over a slab [dlo, dhi): the partials of the strips s whose
+// columns x + d (d in the slab) reach, floor((x + dlo) / 64) ..
+// floor((x + dhi - 1) / 64), summed in strip order, added to g_half.
 // grid: (ceil(X/256), Y, n), block 256.
-__global__ void __launch_bounds__(256) k_soft_gimg(const float* __restrict__ t, int nds, int dlo,
-                                                   int npair, int X, int Y,
-                                                   float* __restrict__ g_half) {
+__global__ void __launch_bounds__(256) k_soft_gright(const float* __restrict__ gr_part, int nstrips,
+                                                     int WP, int dlo, int dhi, int X, int Y,
+                                                     float* __restrict__ g_half) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, pair = blockIdx.z;
   if (x >= X) return;
-  const size_t plane = (size_t)X * Y;
-  float gl = 0.f, gr = 0.f;
-  // disparities in groups of 8, all loads of a group in flight (unconditional,
-  // at clamped indices), then summed in order of j; a column x + d past the
-  // row end contributes nothing (subtracting +0 leaves every value unchanged)
-  for (int j0 = 0; j0 < nds; j0 += 8) {
-    float vl[8], vr[8];
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int j = min(j0 + u, nds - 1);
-      const float* tp = t + ((size_t)j * npair + pair) * plane + (size_t)y * X;
-      vl[u] = tp[x];
-      vr[u] = tp[min(x + dlo + j, X - 1)];
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int j = j0 + u;
-      if (j < nds) {
-        gl += vl[u];
-        gr -= x + dlo + j < X ? vr[u] : 0.f;
-      }
-    }
+  const int s0 = (x + dlo) / 64, s1 = min(nstrips - 1, (x + dhi - 1) / 64);
+  float acc = 0.f;
+  for (int s = s0; s <= s1; ++s) {
+    const int c = x - (s * 64 - dhi + 1);  // in 0 .. WP - 1 for the strips reached
+    acc += gr_part[(((size_t)pair * nstrips + s) * Y + y) * WP + c];
   }
-  g_half[(size_t)(2 * pair) * plane + (size_t)y * X + x] += gl;
-  g_half[(size_t)(2 * pair + 1) * plane + (size_t)y * X + x] += gr;
+  g_half[((size_t)(2 * pair + 1) * Y + y) * X + x] += acc;
 }
 
 // ---------------------------------------------------------- k_soft_gfull
