@@ -214,11 +214,14 @@ def batch_leg(sm, steps):
     lefts = [torch.from_numpy(p.left).to(dev) for p in pairs]
     rights = [torch.from_numpy(p.right).to(dev) for p in pairs]
     outs = [torch.empty((1080, 1920), dtype=torch.int16, device=dev) for _ in pairs]
+    # two contexts: a plan that a graph has captured is kept as it is for the
+    # rest of its context's life (the library cannot see the graph's end), so
+    # the tuned graph gets a context of its own, tuned before any capture
     ctx = sm.Stereo(0)
     stream = torch.cuda.Stream()
 
-    def call():
-        ctx.disparity_batch(lefts, rights, 256, outs=outs)
+    def call(c=None):
+        (c or ctx).disparity_batch(lefts, rights, 256, outs=outs)
 
     def timed(fn):
         a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -232,13 +235,13 @@ def batch_leg(sm, steps):
         torch.cuda.synchronize()
         return a.elapsed_time(b) / steps
 
-    def graphed():
+    def graphed(c=None):
         with torch.cuda.stream(stream):
-            call()  # the plan of this stream exists before the capture
+            call(c)  # the plan of this stream exists before the capture
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g, stream=stream):
-            call()
+            call(c)
         return g
 
     res = {"workload": "8 x 1920x1080 RGB, Dmax=256 (960x540, D=128)"}
@@ -249,15 +252,19 @@ def batch_leg(sm, steps):
                     "graph_pairs_per_s": round(8000.0 / ms_graph, 1),
                     "graph_ms_per_batch": round(ms_graph, 4)}
     del g
+    torch.cuda.synchronize()
+    ctx.close()
+    tuned = sm.Stereo(0)
     with torch.cuda.stream(stream):
-        chosen, cands = ctx.autotune(lefts, rights, 256)
-    g = graphed()
+        chosen, cands = tuned.autotune(lefts, rights, 256)
+    g = graphed(tuned)
     ms_tuned = timed(g.replay)
     res["tuned"] = {"d_chunk_size": chosen, "candidates_ms_per_batch": {str(k): round(v, 4) for k, v in cands.items()},
                     "graph_pairs_per_s": round(8000.0 / ms_tuned, 1),
                     "graph_ms_per_batch": round(ms_tuned, 4)}
     del g
-    ctx.close()
+    torch.cuda.synchronize()
+    tuned.close()
     return res
 
 

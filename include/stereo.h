@@ -232,9 +232,20 @@ typedef struct stereo_soft_params {
   int32_t arm_x;        /* per-side cap of m, n; 0..31                               */
   int32_t arm_y;        /* per-side cap of M, N; 0..63                               */
   int32_t slab;         /* disparities recomputed per backward slab; 0 = automatic   */
+  uint32_t flags;       /* STEREO_SOFT_F_*                                           */
 } stereo_soft_params;
 
-/* tau = 0.1, delta = 13, arm caps 21 and 31, automatic slab. */
+/* stereo_soft_params.flags.  REUSE_FEATURES, for stereo_soft_backward: left
+ * and right hold the same data as in the last stereo_soft_forward made on
+ * this context and stream with these parameters (as in an autograd
+ * backward, which keeps the forward's inputs unchanged); the backward then
+ * reuses that forward's half images, census strings, arms and support sizes
+ * instead of recomputing them.  The library checks that the last feature
+ * pass on the plan was for the same two pointers and recomputes otherwise;
+ * that the data behind them is unchanged is the caller's promise. */
+#define STEREO_SOFT_F_REUSE_FEATURES 1u
+
+/* tau = 0.1, delta = 13, arm caps 21 and 31, automatic slab, no flags. */
 void stereo_soft_default_params(stereo_soft_params* p);
 
 /* Forward of n pairs (1..64): d_hat [n][Y][X] (half-resolution disparity) and

@@ -19,6 +19,7 @@ OK, EINVAL, ENOMEM, EHIP, EUNIMPL = 0, -1, -2, -3, -4
 F_KEEP_INTERMEDIATES = 1
 F_STAGE_TIMING = 2
 F_FULL_RES = 4
+SOFT_F_REUSE_FEATURES = 1
 STAGES = ("downscale", "census_arms", "cost_aggregate_wta", "chunk_min",
           "crosscheck_median_fill", "upscale")
 
@@ -49,7 +50,8 @@ class Params(ctypes.Structure):
 class SoftParams(ctypes.Structure):
     _fields_ = [("size", ctypes.c_uint32), ("tau", ctypes.c_float),
                 ("color_delta", ctypes.c_int32), ("arm_x", ctypes.c_int32),
-                ("arm_y", ctypes.c_int32), ("slab", ctypes.c_int32)]
+                ("arm_y", ctypes.c_int32), ("slab", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
 
 
 class ServerConfig(ctypes.Structure):

@@ -17,7 +17,7 @@ using namespace stereo_dev;
 namespace stereo_host {
 
 constexpr int kSoftMaxPairs = 64;
-constexpr size_t kSlabBudget = size_t(512) << 20;  // dL/dCA + dL/dCA_x planes of a slab
+constexpr size_t kSlabBudget = size_t(1) << 30;  // dL/dCA + dL/dCA_x planes of a slab
 
 struct SoftPlan {
   int n = 0, W = 0, H = 0, Dmax = 0, X = 0, Y = 0, D = 0;
@@ -45,6 +45,9 @@ struct SoftPlan {
   int WP = 0;                  // 64 + nds - 1 columns per partial row
   float* g_half = nullptr;     // [2n][Y][X]
   float2* lam_part = nullptr;  // [lam_count]
+  // images of the last feature pass on this plan (STEREO_SOFT_F_REUSE_FEATURES)
+  const float* feat_left = nullptr;
+  const float* feat_right = nullptr;
   uint64_t last_use = 0;
   hipStream_t owner = nullptr; // the stream the plan serves (plans are never shared
                                // between streams, so calls on two streams may overlap)
@@ -58,6 +61,7 @@ void free_soft_plans(std::vector<SoftPlan*>& plans) {
   plans.clear();
 }
 
+// Plans are shared by calls whose parameters differ in flags only.
 bool same_soft(const stereo_soft_params& a, const stereo_soft_params& b) {
   return a.tau == b.tau && a.color_delta == b.color_delta && a.arm_x == b.arm_x &&
          a.arm_y == b.arm_y && a.slab == b.slab;
@@ -85,6 +89,7 @@ int soft_checks(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_soft_
   if (p->arm_x < 0 || p->arm_x > 31 || p->arm_y < 0 || p->arm_y > 63)
     return fail(c, STEREO_EINVAL, "soft head arm caps: arm_x in 0..31, arm_y in 0..63");
   if (p->slab < 0) return fail(c, STEREO_EINVAL, "slab must be >= 0");
+  if (p->flags & ~STEREO_SOFT_F_REUSE_FEATURES) return fail(c, STEREO_EINVAL, "unknown flags");
   return 0;
 }
 
@@ -218,7 +223,9 @@ int get_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_sof
 
 // Features shared by forward and backward: float and uint8 half images,
 // census and arms (k_feat of the integer path), padded pixel planes, 1/|S|.
-void soft_features(const SoftPlan& pl, const float* left, const float* right, hipStream_t s) {
+void soft_features(SoftPlan& pl, const float* left, const float* right, hipStream_t s) {
+  pl.feat_left = left;
+  pl.feat_right = right;
   const int X = pl.X, Y = pl.Y, n2 = 2 * pl.n;
   hipLaunchKernelGGL(k_soft_prep, dim3((X + 63) / 64, (Y + 3) / 4, n2), dim3(64, 4), 0, s, left,
                      right, pl.W, pl.H, X, Y, pl.half_f, pl.half_u8);
@@ -256,10 +263,11 @@ void launch_soft_agg(const SoftPlan& pl, const SoftArgs& a, hipStream_t s) {
 }
 
 int soft_prologue(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_soft_params* params,
-                  hipStream_t s, SoftPlan** pl) {
+                  hipStream_t s, SoftPlan** pl, uint32_t* flags = nullptr) {
   stereo_soft_params p;
   int rc = soft_checks(c, n, W, H, Dmax, params, &p);
   if (rc) return rc;
+  if (flags) *flags = p.flags;
   HIP_TRY(c, hipSetDevice(c->device));
   return get_soft_plan(c, n, W, H, Dmax, p, s, pl);
 }
@@ -326,6 +334,7 @@ void stereo_soft_default_params(stereo_soft_params* p) {
   p->arm_x = 21;
   p->arm_y = 31;
   p->slab = 0;
+  p->flags = 0;
 }
 
 int stereo_soft_forward(stereo_ctx* c, const float* left, const float* right, int n, int W, int H,
@@ -355,10 +364,12 @@ int stereo_soft_backward(stereo_ctx* c, const float* left, const float* right, i
       !g_lambdas)
     return fail(c, STEREO_EINVAL, "null pointer");
   SoftPlan* pl = nullptr;
-  int rc = soft_prologue(c, n, W, H, Dmax, params, stream, &pl);
+  uint32_t flags = 0;
+  int rc = soft_prologue(c, n, W, H, Dmax, params, stream, &pl, &flags);
   if (rc) return rc;
   const int X = pl->X, Y = pl->Y, npix = X * Y;
-  soft_features(*pl, left, right, stream);
+  if (!(flags & STEREO_SOFT_F_REUSE_FEATURES) || pl->feat_left != left || pl->feat_right != right)
+    soft_features(*pl, left, right, stream);
   const float zc = (float)(std::ldexp(1.0, -pl->fxk) * 1.4426950408889634 / pl->p.tau);
   hipLaunchKernelGGL(k_soft_bprep, dim3((npix + 255) / 256, pl->n), dim3(256), 0, stream,
                      pl->inv_size, lse2, d_hat, g_dhat, npix, zc, 1.f / pl->p.tau, pl->pc);

@@ -16,7 +16,17 @@ from __future__ import annotations
 
 import torch
 
-from .binding import SoftParams
+from .binding import SOFT_F_REUSE_FEATURES, SoftParams, soft_default_params
+
+
+def _reusing(params: SoftParams | None) -> SoftParams:
+    """params (defaults when None) with REUSE_FEATURES set: the backward
+    gets the forward's saved inputs, which autograd keeps unchanged, so the
+    forward's features are reused whenever the plan still holds them (the
+    library checks that the last feature pass was for the same tensors)."""
+    p = soft_default_params() if params is None else SoftParams.from_buffer_copy(params)
+    p.flags |= SOFT_F_REUSE_FEATURES
+    return p
 
 
 class SoftArgmin(torch.autograd.Function):
@@ -33,7 +43,8 @@ class SoftArgmin(torch.autograd.Function):
     def backward(fctx, g_dhat, _g_lse):
         left, right, lambdas, d_hat, lse2 = fctx.saved_tensors
         g_left, g_right, g_lam = fctx.stereo.soft_backward(
-            left, right, lambdas, fctx.dmax, d_hat, lse2, g_dhat.contiguous(), fctx.params)
+            left, right, lambdas, fctx.dmax, d_hat, lse2, g_dhat.contiguous(),
+            _reusing(fctx.params))
         return g_left, g_right, g_lam, None, None, None
 
 

@@ -106,3 +106,36 @@ def test_noalloc_makes_no_device_allocation_and_refuses_oversize(sm):
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), ref.cpu().numpy())
     ctx.close()
+
+
+def test_noalloc_under_graph_capture(sm):
+    """The caller this entry point is for: code under graph capture.  The call
+    is captured in a HIP graph and replayed three times; between replays an
+    eager no-allocation call of another shape overwrites the fixed array, and
+    each replay (which re-initialises it) still gives stereo_disparity's map."""
+    ctx = sm.Stereo(0)
+    pair = make_pair(320, 240, 32, segments=6, seed=43)
+    other = make_pair(200, 120, 48, segments=4, seed=44)
+    lt, rt = dev(pair.left), dev(pair.right)
+    ol, orr = dev(other.left), dev(other.right)
+    out = torch.empty((240, 320), dtype=torch.int16, device="cuda")
+    oout = torch.empty((120, 200), dtype=torch.int16, device="cuda")
+    ref = ctx.disparity(lt, rt, 32).cpu().numpy()
+    s = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    say("[noalloc] capture 320x240 Dmax 32")
+    with torch.cuda.graph(g, stream=s):
+        rc = call_noalloc(sm, ctx, lt, rt, 32, out)
+    assert rc == 0, ctx.last_error()
+    for k in range(3):
+        out.fill_(-7)
+        assert call_noalloc(sm, ctx, ol, orr, 48, oout) == 0, ctx.last_error()
+        torch.cuda.synchronize()
+        say(f"[noalloc] replay {k}")
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), ref), k
+    del g
+    torch.cuda.synchronize()
+    ctx.close()
