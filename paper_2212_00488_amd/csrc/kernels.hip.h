@@ -348,6 +348,15 @@ __global__ void __launch_bounds__(256) k_plan_init(uint32_t* __restrict__ zero, 
   }
 }
 
+// Byte offset of k_match's row buffers in its LDS block (after the table).
+constexpr int kMatchOffRow = ((kTab * 2 + 15) / 16) * 16;
+
+// Bytes of k_match's LDS block with NS sub-passes and a plane of `rows`
+// rows (plane row 0 is the zero row).
+__host__ __device__ constexpr int match_lds_bytes(int ns, int rows) {
+  return kMatchOffRow + kWaves * ns * 128 * 4 + kWaves * 64 * 4 + rows * 64 * 4;
+}
+
 // LDS rows of the k_match plane for NS sub-passes of 128 row-buffer columns.
 __host__ __device__ constexpr int plane_rows(int ns) {
   return (kLdsBytes - kTab * 2 - kWaves * 64 * 4 - kWaves * ns * 128 * 4) / 256 - 2;
@@ -393,11 +402,16 @@ template <int NS, int KMAX, bool DBG>
 __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   constexpr int PR = plane_rows(NS);
   // One LDS block carved at constant offsets, the cost table first (LDS
-  // address 0), so table addresses fold into the read's offset field.
-  constexpr int kOffRow = ((kTab * 2 + 15) / 16) * 16;
+  // address 0), so table addresses fold into the read's offset field.  The
+  // block is dynamic, sized by the host to the plane rows the plan reads
+  // (match_lds_bytes), at most PR + 1: LDS the plan does not need is left to
+  // the kernels of other streams (the next frame's), which can then share
+  // the CU.
+  constexpr int kOffRow = kMatchOffRow;
   constexpr int kOffSeg = kOffRow + kWaves * NS * 128 * 4;
   constexpr int kOffPlane = kOffSeg + kWaves * 64 * 4;
-  __shared__ __align__(16) uint8_t s_lds[kOffPlane + (PR + 1) * 64 * 4];
+  static_assert(kOffPlane + (PR + 1) * 64 * 4 <= kLdsBytes, "LDS block");
+  extern __shared__ __align__(16) uint8_t s_lds[];
   uint16_t* s_tab = reinterpret_cast<uint16_t*>(s_lds);
   auto s_row = reinterpret_cast<uint32_t(*)[NS * 128]>(s_lds + kOffRow);
   auto s_seg = reinterpret_cast<uint32_t(*)[64]>(s_lds + kOffSeg);

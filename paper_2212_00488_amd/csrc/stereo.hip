@@ -444,14 +444,30 @@ MatchArgs match_args(const Plan& pl, int dlo, int dhi, int csize) {
   return a;
 }
 
+// k_match with KMAX = KM: its LDS block holds the plane rows the plan's
+// bands write (band rows + 1) or its window step reads (o0 + 16 KMAX + 1),
+// whichever is more; the rest of the CU's LDS stays free for other streams.
+template <int NS, int KM, bool DBG>
+void launch_match_km(const Plan& pl, const MatchArgs& a, dim3 grid, hipStream_t s) {
+  const int brows = pl.nbands == 1 ? pl.Y : std::min(pl.Y, (pl.Y + pl.nbands - 1) / pl.nbands + 2 * pl.p.arm_y);
+  const int o0max = pl.nbands == 1 ? 0 : pl.p.arm_y;
+  const int rows = std::max(brows, o0max + kWaves * KM) + 1;
+  static const hipError_t attr = hipFuncSetAttribute(
+      reinterpret_cast<const void*>(&k_match<NS, KM, DBG>),
+      hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+  (void)attr;
+  hipLaunchKernelGGL((k_match<NS, KM, DBG>), grid, dim3(kThreads),
+                     (size_t)match_lds_bytes(NS, rows), s, a);
+}
+
 template <int NS, bool DBG>
 void launch_match_k(const Plan& pl, const MatchArgs& a, dim3 grid, hipStream_t s) {
   switch (pl.kmax) {
-    case 8: hipLaunchKernelGGL((k_match<NS, 8, DBG>), grid, dim3(kThreads), 0, s, a); break;
-    case 16: hipLaunchKernelGGL((k_match<NS, 16, DBG>), grid, dim3(kThreads), 0, s, a); break;
-    case 24: hipLaunchKernelGGL((k_match<NS, 24, DBG>), grid, dim3(kThreads), 0, s, a); break;
-    case 32: hipLaunchKernelGGL((k_match<NS, 32, DBG>), grid, dim3(kThreads), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_match<NS, kKMax, DBG>), grid, dim3(kThreads), 0, s, a); break;
+    case 8: launch_match_km<NS, 8, DBG>(pl, a, grid, s); break;
+    case 16: launch_match_km<NS, 16, DBG>(pl, a, grid, s); break;
+    case 24: launch_match_km<NS, 24, DBG>(pl, a, grid, s); break;
+    case 32: launch_match_km<NS, 32, DBG>(pl, a, grid, s); break;
+    default: launch_match_km<NS, kKMax, DBG>(pl, a, grid, s); break;
   }
 }
 
