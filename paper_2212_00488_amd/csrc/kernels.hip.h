@@ -162,6 +162,10 @@ __global__ void __launch_bounds__(256) k_prep(PairPtrs pp, int W, int H, int X, 
 constexpr int kFeatRows = 16;    // output rows per k_feat workgroup (one pixel per thread)
 constexpr int kMaxArm = 127;
 
+// Columns left of a 64-column strip in k_match's row buffer for a horizontal
+// arm cap: arm + 1, rounded up to even (the row pass takes column pairs).
+__host__ __device__ constexpr int row_halo(int arm_cap) { return (arm_cap + 2) & ~1; }
+
 // Length of one arm of a pixel of value c: the number of steps t = 1, 2, ...
 // along the axis, taken without a break, whose pixel satisfies |I - c| < delta,
 // at most lim.  p points at the pixel in an LDS tile and STRIDE is the tile
@@ -216,6 +220,10 @@ __device__ __forceinline__ int arm_len(const uint8_t* p, int c, int delta, int c
 // Pixels go to pk (gray * 2 | census << 16, may be NULL) and to the two copies
 // of pk16 (gray | census << 8, may be NULL; the second copy copy16 elements
 // after the first, one pixel to the right); pitch XP, column x at pad + x.
+// xoff (may be NULL) takes, for k_match's row pass, the byte offsets in a
+// wave's row buffer of the row-prefix entries that bound CA_x (Eq. 7) at x:
+// 4 (x mod 64 + h - m - 1) in bits 0..15 and 4 (x mod 64 + h + n) in bits
+// 16..31, h = row_halo(cap) of the image; pitch XA like arms.
 // Two workgroups share a CU only while a wave holds at most 80 SGPRs; the
 // waves-per-EU bound keeps the compiler under that (above it the kernel took
 // a fifth longer).
@@ -223,7 +231,8 @@ __device__ __forceinline__ int arm_len(const uint8_t* p, int c, int delta, int c
 __global__ void __launch_bounds__(64 * kFeatRows) __attribute__((amdgpu_waves_per_eu(8)))
 k_feat(const uint8_t* __restrict__ half, int X, int Y, int delta, int arm_x_l, int arm_x_r,
        int arm_y, int XP, int pad, int XA, uint32_t* __restrict__ pk,
-       uint32_t* __restrict__ arms, uint16_t* __restrict__ pk16, size_t copy16) {
+       uint32_t* __restrict__ arms, uint32_t* __restrict__ xoff, uint16_t* __restrict__ pk16,
+       size_t copy16) {
   constexpr int TXW = 64 + 2 * (kMaxArm + kArmPad);
   __shared__ uint8_t tx[kFeatRows + 2][TXW];
   __shared__ uint8_t ty[kFeatRows + 2 * (kMaxArm + kArmPad)][64];
@@ -263,6 +272,10 @@ k_feat(const uint8_t* __restrict__ half, int X, int Y, int delta, int arm_x_l, i
     if (pk) pk[((size_t)img * Y + y) * XP + pad + x] = (uint32_t)(2 * c) | ((uint32_t)bits << 16);
     arms[((size_t)img * Y + y) * XA + x] =
         (uint32_t)m | ((uint32_t)n << 8) | ((uint32_t)M << 16) | ((uint32_t)N << 24);
+    if (xoff) {
+      const uint32_t lh = (uint32_t)(lx + row_halo(arm_x));
+      xoff[((size_t)img * Y + y) * XA + x] = 4u * (lh - (uint32_t)m - 1u) | 4u * (lh + (uint32_t)n) << 16;
+    }
     p16 = (uint32_t)c | (uint32_t)bits << 8;
   }
   if (pk16) {
@@ -348,13 +361,14 @@ __global__ void __launch_bounds__(256) k_plan_init(uint32_t* __restrict__ zero, 
   }
 }
 
-// Byte offset of k_match's row buffers in its LDS block (after the table).
-constexpr int kMatchOffRow = ((kTab * 2 + 15) / 16) * 16;
+// Bytes of k_match's static LDS: the cost table.
+constexpr int kMatchTabBytes = ((kTab * 2 + 15) / 16) * 16;
 
-// Bytes of k_match's LDS block with NS sub-passes and a plane of `rows`
-// rows (plane row 0 is the zero row).
+// Bytes of k_match's dynamic LDS block with NS sub-passes and a plane of
+// `rows` rows (plane row 0 is the zero row): row buffers, segment totals and
+// the plane.
 __host__ __device__ constexpr int match_lds_bytes(int ns, int rows) {
-  return kMatchOffRow + kWaves * ns * 128 * 4 + kWaves * 64 * 4 + rows * 64 * 4;
+  return kWaves * ns * 128 * 4 + kWaves * 64 * 4 + rows * 64 * 4;
 }
 
 // LDS rows of the k_match plane for NS sub-passes of 128 row-buffer columns.
@@ -365,6 +379,7 @@ __host__ __device__ constexpr int plane_rows(int ns) {
 struct MatchArgs {
   const uint16_t* pk;     // [2][2*npair][Y][XP]  padded: gray | census << 8, two copies
   const uint32_t* arms;   // [2*npair][Y][XA]  zero past column X
+  const uint32_t* xoff;   // [2*npair][Y][XA]  row-buffer offsets (k_feat), zero past column X
   const uint16_t* tab;    // [kTabRows][kTabPitch]
   uint32_t* keys;         // [npair][nchunk][2][nk]  (min CA) << dbits | argmin d
   int X, Y, XP, pad, XA, nk, arm_x, arm_x_r, arm_y;
@@ -401,18 +416,18 @@ struct MatchArgs {
 template <int NS, int KMAX, bool DBG>
 __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   constexpr int PR = plane_rows(NS);
-  // One LDS block carved at constant offsets, the cost table first (LDS
-  // address 0), so table addresses fold into the read's offset field.  The
-  // block is dynamic, sized by the host to the plane rows the plan reads
-  // (match_lds_bytes), at most PR + 1: LDS the plan does not need is left to
-  // the kernels of other streams (the next frame's), which can then share
-  // the CU.
-  constexpr int kOffRow = kMatchOffRow;
+  // The cost table is the kernel's static LDS, at LDS address 0, so table
+  // addresses fold into the read's offset field.  The rest is one dynamic
+  // block carved at constant offsets, sized by the host to the plane rows the
+  // plan reads (match_lds_bytes), at most PR + 1: LDS the plan does not need
+  // is left to the kernels of other streams (the next frame's), which can
+  // then share the CU.
+  constexpr int kOffRow = 0;
   constexpr int kOffSeg = kOffRow + kWaves * NS * 128 * 4;
   constexpr int kOffPlane = kOffSeg + kWaves * 64 * 4;
-  static_assert(kOffPlane + (PR + 1) * 64 * 4 <= kLdsBytes, "LDS block");
+  static_assert(kMatchTabBytes + kOffPlane + (PR + 1) * 64 * 4 <= kLdsBytes, "LDS block");
+  __shared__ __align__(16) uint16_t s_tab[kMatchTabBytes / 2];
   extern __shared__ __align__(16) uint8_t s_lds[];
-  uint16_t* s_tab = reinterpret_cast<uint16_t*>(s_lds);
   auto s_row = reinterpret_cast<uint32_t(*)[NS * 128]>(s_lds + kOffRow);
   auto s_seg = reinterpret_cast<uint32_t(*)[64]>(s_lds + kOffSeg);
   uint32_t* s_plane = reinterpret_cast<uint32_t*>(s_lds + kOffPlane);  // row 0 = zeros
@@ -441,10 +456,10 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   const int nb = yb - ya, o0 = y0 - ya, o1 = y1 - ya;
   const int d0 = a.dlo + chunk * a.csize, d1 = min(a.dhi, d0 + a.csize);
   // row buffer starts at column x0 - hx (even); hx covers this base's arms
-  const int hx = ((base ? a.arm_x_r : a.arm_x) + 2) & ~1;
+  const int hx = row_halo(base ? a.arm_x_r : a.arm_x);
   const int sgn = base ? 1 : -1;       // other-image column is x + sgn * d
   const __amdgpu_buffer_rsrc_t rb = buffer_rsrc(a.pk, a.pk_bytes);
-  const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(a.arms, a.arms_bytes);
+  const __amdgpu_buffer_rsrc_t ra = buffer_rsrc(a.xoff, a.arms_bytes);
   const uint32_t img_b = (uint32_t)(2 * pair + base), img_o = (uint32_t)(2 * pair + (base ^ 1));
   const uint32_t pkrow = (uint32_t)a.XP * 2u, armrow = (uint32_t)a.XA * 4u;
   const bool dbg = DBG && pair == 0 && base == a.dbg_base;
@@ -567,8 +582,10 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
         }
       }
       WAVE_LDS_ORDER();
-      const int m = am & 255u, n = (am >> 8) & 255u;
-      const uint32_t cax = s_row[wave][lane + hx + n] - s_row[wave][lane + hx - m - 1];
+      // am: byte offsets of entries x + n and x - m - 1 in the row buffer
+      const uint8_t* rw = reinterpret_cast<const uint8_t*>(s_row[wave]);
+      const uint32_t cax = *reinterpret_cast<const uint32_t*>(rw + (am >> 16)) -
+                           *reinterpret_cast<const uint32_t*>(rw + (am & 0xffffu));
       WAVE_LDS_ORDER();
       if (DBG && dbg && d == a.dlo && x < X && y >= y0 && y < y1) a.dbg_cax[(size_t)y * X + x] = cax;
       return cax;

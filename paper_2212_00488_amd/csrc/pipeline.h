@@ -28,6 +28,8 @@ struct Plan {
   uint16_t* pk = nullptr;     // [2][2*npair][Y][XP]  gray | census<<8, zero padding; the
                               // second copy one column to the right
   uint32_t* arms = nullptr;   // [2*npair][Y][XA]  zero padding
+  uint32_t* xoff = nullptr;   // [2*npair][Y][XA]  k_match row-buffer offsets of the
+                              // horizontal arm ends, zero padding
   uint16_t* tab = nullptr;    // [7][kTabPitch]
   uint32_t* keys = nullptr;   // [npair][nchunk][2][Y][X]
   int16_t* disp = nullptr;    // [2*npair][Y][X]

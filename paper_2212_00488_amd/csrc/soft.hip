@@ -231,7 +231,7 @@ void soft_features(SoftPlan& pl, const float* left, const float* right, hipStrea
                      right, pl.W, pl.H, X, Y, pl.half_f, pl.half_u8);
   hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + kFeatRows - 1) / kFeatRows, n2),
                      dim3(64, kFeatRows), 0, s, pl.half_u8, X, Y, pl.p.color_delta, pl.p.arm_x,
-                     pl.p.arm_x, pl.p.arm_y, X, 0, pl.XA, pl.pk, pl.arms, nullptr, 0);
+                     pl.p.arm_x, pl.p.arm_y, X, 0, pl.XA, pl.pk, pl.arms, nullptr, nullptr, 0);
   hipLaunchKernelGGL(k_soft_pack, dim3((X + 255) / 256, Y, n2), dim3(256), 0, s, pl.half_f, pl.pk,
                      X, Y, pl.XS, pl.pads, pl.sp);
   hipLaunchKernelGGL(k_soft_size, dim3((X + 63) / 64, (Y + kSizeRows - 1) / kSizeRows, pl.n),

@@ -239,7 +239,7 @@ int tuned_csize(const stereo_ctx* c, int W, int H, int Dmax, int npair, const st
 // Device bytes of a plan's block and of its pixel (pk, both copies) and arm
 // planes, for the geometry already in pl.
 struct PlanBytes {
-  size_t total, pk, arms;
+  size_t total, pk, arms;  // arms: each of the arms and xoff planes
 };
 
 PlanBytes plan_bytes(const Plan& pl) {
@@ -250,7 +250,7 @@ PlanBytes plan_bytes(const Plan& pl) {
   PlanBytes b;
   b.pk = 2 * npk * 2;
   b.arms = nar * 4;
-  b.total = al(2 * npair * n) + al(b.pk) + al(b.arms) + al(kTab * 2) +
+  b.total = al(2 * npair * n) + al(b.pk) + 2 * al(b.arms) + al(kTab * 2) +
             al((size_t)npair * pl.nchunk * 2 * nk * 4) + al(2 * npair * nk * 2) +
             al(2 * npair * nk * 4) + al(npair * n) + al(npair * n * 2) + al(npair * n * 2);
   return b;
@@ -289,6 +289,7 @@ void plan_carve_and_init(Plan& pl, void* base, hipStream_t s) {
   pl.half = carve<uint8_t>(cur, 2 * npair * n);
   pl.pk = carve<uint16_t>(cur, b.pk / 2);
   pl.arms = carve<uint32_t>(cur, b.arms / 4);
+  pl.xoff = carve<uint32_t>(cur, b.arms / 4);
   pl.tab = carve<uint16_t>(cur, kTab);
   pl.keys = carve<uint32_t>(cur, npair * pl.nchunk * 2 * nk);
   pl.disp = carve<int16_t>(cur, 2 * npair * nk);
@@ -300,8 +301,8 @@ void plan_carve_and_init(Plan& pl, void* base, hipStream_t s) {
   for (int i = 0; i < 256; ++i) t.ad[i] = pl.lut_ad[i];
   for (int i = 0; i < 7; ++i) t.mc[i] = pl.lut_mc[i];
   t.cmax = (uint16_t)pl.cmax;
-  // pk and arms are adjacent in the block: one cleared range covers both
-  const size_t nzero = (size_t)(reinterpret_cast<char*>(pl.arms) + b.arms -
+  // pk, arms and xoff are adjacent in the block: one cleared range covers them
+  const size_t nzero = (size_t)(reinterpret_cast<char*>(pl.xoff) + b.arms -
                                 reinterpret_cast<char*>(pl.pk)) / 4;
   const unsigned blocks = (unsigned)std::min<size_t>(2048, (nzero + 1023) / 1024 + 1);
   hipLaunchKernelGGL(k_plan_init, dim3(blocks), dim3(256), 0, s,
@@ -432,7 +433,7 @@ void set_tuned(stereo_ctx* c, int W, int H, int Dmax, int npair, const stereo_pa
 
 MatchArgs match_args(const Plan& pl, int dlo, int dhi, int csize) {
   MatchArgs a{};
-  a.pk = pl.pk; a.arms = pl.arms; a.tab = pl.tab; a.keys = pl.keys;
+  a.pk = pl.pk; a.arms = pl.arms; a.xoff = pl.xoff; a.tab = pl.tab; a.keys = pl.keys;
   a.X = pl.X; a.Y = pl.Y; a.XP = pl.XP; a.pad = pl.pad; a.XA = pl.XA; a.nk = pl.nk;
   a.arm_x = pl.p.arm_x; a.arm_x_r = pl.p.arm_x_r; a.arm_y = pl.p.arm_y; a.dbits = pl.dbits;
   a.copy_bytes = (uint32_t)((size_t)2 * pl.npair * pl.Y * pl.XP * 2);
@@ -454,7 +455,7 @@ void launch_match_km(const Plan& pl, const MatchArgs& a, dim3 grid, hipStream_t 
   const int rows = std::max(brows, o0max + kWaves * KM) + 1;
   static const hipError_t attr = hipFuncSetAttribute(
       reinterpret_cast<const void*>(&k_match<NS, KM, DBG>),
-      hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes);
+      hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes - kMatchTabBytes);
   (void)attr;
   hipLaunchKernelGGL((k_match<NS, KM, DBG>), grid, dim3(kThreads),
                      (size_t)match_lds_bytes(NS, rows), s, a);
@@ -518,7 +519,7 @@ int run(stereo_ctx* c, Plan& pl, const PairPtrs& pp, int npair, bool keep, bool 
   hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + kFeatRows - 1) / kFeatRows, 2 * npair),
                      dim3(64, kFeatRows), 0,
                      s, pl.half, X, Y, pl.p.color_delta, pl.p.arm_x, pl.p.arm_x_r, pl.p.arm_y,
-                     pl.XP, pl.pad, pl.XA, nullptr, pl.arms, pl.pk,
+                     pl.XP, pl.pad, pl.XA, nullptr, pl.arms, pl.xoff, pl.pk,
                      (size_t)2 * npair * Y * pl.XP);
   mark(2);
   launch_match(pl, match_args(pl, 0, pl.D, pl.csize), npair, s);
