@@ -501,8 +501,10 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
   // is one instruction (one scalar operand per vector instruction)
   uint32_t vdbits = (uint32_t)a.dbits;
   __asm__ volatile("" : "+v"(vdbits));
-  uint32_t k8 = 8u;  // shift operand of the SDWA arm extraction below
-  __asm__ volatile("" : "+v"(k8));
+  // byte selector of v_perm: bytes 0 and 2 of marm (M of two rows) to bytes
+  // 1 and 3, zeros to bytes 0 and 2
+  uint32_t kpermM = 0x020c000cu;
+  __asm__ volatile("" : "+v"(kpermM));
   // byte offset of this lane's first column pair inside a padded pk row
   const uint32_t vb = (uint32_t)(a.pad + x0 - hx + 2 * lane) * 2u;
   __syncthreads();
@@ -614,9 +616,10 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
         for (int s = 0; s < NS; ++s) pr[i][s] = wave_scan_incl(c0[i][s] + c1[i][s]);
 #pragma unroll
       for (int i = 0; i < kRowBatch; ++i) {
-        if (i > 0 && r + i >= r1) break;
+        // a row past the segment end (its last row again) is evaluated but
+        // not stored: the plane row belongs to the next segment
         run += finish_row(r + i, c0[i], c1[i], pr[i], in[i].am);
-        s_plane[(r + i + 1) * 64 + lane] = run;
+        if (i == 0 || r + i < r1) s_plane[(r + i + 1) * 64 + lane] = run;
       }
     };
     // The next batch is loaded unconditionally (past the segment end it
@@ -655,17 +658,14 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
 #pragma unroll
     for (int j = 0; j < KMAX / 2; ++j) {
       // byte offsets of plane rows +N and -(M+1) from the output rows 2j and
-      // 2j+1: a plane row is 256 bytes, so each offset is one arm byte of
-      // marm[j] moved to bits 8..15, one SDWA instruction each.  Volatile
-      // asm keeps them inside the d loop (hoisted, they would need 64 VGPRs).
-      uint32_t off[4];
-      __asm__ volatile("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD "
-                       "src0_sel:DWORD src1_sel:BYTE_0" : "=v"(off[0]) : "v"(marm[j]), "v"(k8));
-      __asm__ volatile("v_and_b32 %0, 0xff00, %1" : "=v"(off[1]) : "v"(marm[j]));
-      __asm__ volatile("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD "
-                       "src0_sel:DWORD src1_sel:BYTE_2" : "=v"(off[2]) : "v"(marm[j]), "v"(k8));
-      __asm__ volatile("v_lshlrev_b32_sdwa %0, %2, %1 dst_sel:DWORD dst_unused:UNUSED_PAD "
-                       "src0_sel:DWORD src1_sel:BYTE_3" : "=v"(off[3]) : "v"(marm[j]), "v"(k8));
+      // 2j+1: a plane row is 256 bytes, so an offset is an arm byte in bits
+      // 8..15 of a 16-bit half: nw holds N of both rows in its halves, mw
+      // holds M; each read address is then one SDWA add or subtract.
+      // Volatile asm keeps them inside the d loop (hoisted, they would need
+      // 32 VGPRs).
+      uint32_t nw, mw;
+      __asm__ volatile("v_and_b32 %0, 0xff00ff00, %1" : "=v"(nw) : "v"(marm[j]));
+      __asm__ volatile("v_perm_b32 %0, 0, %1, %2" : "=v"(mw) : "v"(marm[j]), "v"(kpermM));
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int k = 2 * j + h;
@@ -673,8 +673,9 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
         // reaches above the band); the per-row part k * 4096 bytes becomes
         // the reads' immediate offset
         const uint8_t* row = s_lds + kOffPlane + k * kWaves * 256 + fin_b;
-        const uint32_t ca = *reinterpret_cast<const uint32_t*>(row + off[2 * h + 1]) -
-                            *reinterpret_cast<const uint32_t*>(row - 256 - off[2 * h]);
+        const uint32_t on = h ? nw >> 16 : nw & 0xffffu, om = h ? mw >> 16 : mw & 0xffffu;
+        const uint32_t ca = *reinterpret_cast<const uint32_t*>(row + on) -
+                            *reinterpret_cast<const uint32_t*>(row - 256 - om);
         const uint32_t kv = (ca << vdbits) | (uint32_t)d;
         key[k] = kv < key[k] ? kv : key[k];
       }
