@@ -617,9 +617,12 @@ __global__ void __launch_bounds__(kThreads) k_match(MatchArgs a) {
 #pragma unroll
       for (int i = 0; i < kRowBatch; ++i) {
         // a row past the segment end (its last row again) is evaluated but
-        // not stored: the plane row belongs to the next segment
-        run += finish_row(r + i, c0[i], c1[i], pr[i], in[i].am);
-        if (i == 0 || r + i < r1) s_plane[(r + i + 1) * 64 + lane] = run;
+        // neither added nor stored: the plane row belongs to the next segment
+        const uint32_t cax = finish_row(r + i, c0[i], c1[i], pr[i], in[i].am);
+        if (i == 0 || r + i < r1) {
+          run += cax;
+          s_plane[(r + i + 1) * 64 + lane] = run;
+        }
       }
     };
     // The next batch is loaded unconditionally (past the segment end it
