@@ -18,8 +18,8 @@
 //   backward  k_soft_bprep  per-pixel constants of dL/dCA
 //             k_soft_agg    (GCA mode) recomputes CA for a slab of d and
 //                           writes dL/dCA planes
-//             k_soft_tcol   transposed vertical window sums (difference
-//                           arrays in an LDS ring, one pass down each column)
+//             k_soft_tcol   transposed vertical window sums (integer difference
+//                           arrays over bands of output rows, LDS atomics)
 //             k_soft_tr     transposed horizontal window sums back to dL/dC,
 //                           then dC/d(dI), dC/d(lambda) per pixel, summed over
 //                           the slab into the half-image gradients
