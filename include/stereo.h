@@ -242,8 +242,18 @@ typedef struct stereo_soft_params {
  * reuses that forward's half images, census strings, arms and support sizes
  * instead of recomputing them.  The library checks that the last feature
  * pass on the plan was for the same two pointers and recomputes otherwise;
- * that the data behind them is unchanged is the caller's promise. */
+ * that the data behind them is unchanged is the caller's promise.  If that
+ * forward also saved its weights (SAVE_WEIGHTS) for the same left, right and
+ * lambdas pointers, the backward forms dL/dCA from them instead of
+ * recomputing the aggregate; lambdas must then hold the forward's values too.
+ * SAVE_WEIGHTS, for stereo_soft_forward: keep the softmax weight of every
+ * pixel and disparity (n * X * Y * D floats of the context's scratch, in the
+ * planes the backward's slabs use; ignored when one slab cannot hold all D)
+ * for a following backward with REUSE_FEATURES.  Any later forward or
+ * backward with other inputs on the same context, stream and parameters
+ * replaces or drops them. */
 #define STEREO_SOFT_F_REUSE_FEATURES 1u
+#define STEREO_SOFT_F_SAVE_WEIGHTS 2u
 
 /* tau = 0.1, delta = 13, arm caps 21 and 31, automatic slab, no flags. */
 void stereo_soft_default_params(stereo_soft_params* p);

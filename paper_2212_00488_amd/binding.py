@@ -20,6 +20,7 @@ F_KEEP_INTERMEDIATES = 1
 F_STAGE_TIMING = 2
 F_FULL_RES = 4
 SOFT_F_REUSE_FEATURES = 1
+SOFT_F_SAVE_WEIGHTS = 2
 STAGES = ("downscale", "census_arms", "cost_aggregate_wta", "chunk_min",
           "crosscheck_median_fill", "upscale")
 

@@ -48,6 +48,13 @@ struct SoftPlan {
   // images of the last feature pass on this plan (STEREO_SOFT_F_REUSE_FEATURES)
   const float* feat_left = nullptr;
   const float* feat_right = nullptr;
+  // inputs of the last forward, when it saved its weights e_d in the gca
+  // planes (STEREO_SOFT_F_SAVE_WEIGHTS, all D in one slab); any other
+  // forward, and a backward that recomputes the slabs, clears wts_valid
+  bool wts_valid = false;
+  const float* wts_left = nullptr;
+  const float* wts_right = nullptr;
+  const float* wts_lam = nullptr;
   uint64_t last_use = 0;
   hipStream_t owner = nullptr; // the stream the plan serves (plans are never shared
                                // between streams, so calls on two streams may overlap)
@@ -89,7 +96,8 @@ int soft_checks(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_soft_
   if (p->arm_x < 0 || p->arm_x > 31 || p->arm_y < 0 || p->arm_y > 63)
     return fail(c, STEREO_EINVAL, "soft head arm caps: arm_x in 0..31, arm_y in 0..63");
   if (p->slab < 0) return fail(c, STEREO_EINVAL, "slab must be >= 0");
-  if (p->flags & ~STEREO_SOFT_F_REUSE_FEATURES) return fail(c, STEREO_EINVAL, "unknown flags");
+  if (p->flags & ~(STEREO_SOFT_F_REUSE_FEATURES | STEREO_SOFT_F_SAVE_WEIGHTS))
+    return fail(c, STEREO_EINVAL, "unknown flags");
   return 0;
 }
 
@@ -344,10 +352,20 @@ int stereo_soft_forward(stereo_ctx* c, const float* left, const float* right, in
   c->err.clear();
   if (!left || !right || !lambdas || !d_hat || !lse2) return fail(c, STEREO_EINVAL, "null pointer");
   SoftPlan* pl = nullptr;
-  int rc = soft_prologue(c, n, W, H, Dmax, params, stream, &pl);
+  uint32_t flags = 0;
+  int rc = soft_prologue(c, n, W, H, Dmax, params, stream, &pl, &flags);
   if (rc) return rc;
   soft_features(*pl, left, right, stream);
-  launch_soft_agg<false>(*pl, soft_args(*pl, lambdas, 0, pl->D, pl->csize), stream);
+  SoftArgs a = soft_args(*pl, lambdas, 0, pl->D, pl->csize);
+  // the weights of all D fit the gca planes only when one slab covers D
+  pl->wts_valid = (flags & STEREO_SOFT_F_SAVE_WEIGHTS) && pl->nds >= pl->D;
+  if (pl->wts_valid) {
+    a.wts = pl->gca;
+    pl->wts_left = left;
+    pl->wts_right = right;
+    pl->wts_lam = lambdas;
+  }
+  launch_soft_agg<false>(*pl, a, stream);
   const int npix = pl->X * pl->Y;
   hipLaunchKernelGGL(k_soft_merge, dim3((npix + 255) / 256, pl->n), dim3(256), 0, stream, pl->part,
                      pl->nchunk, npix, d_hat, lse2);
@@ -368,23 +386,40 @@ int stereo_soft_backward(stereo_ctx* c, const float* left, const float* right, i
   int rc = soft_prologue(c, n, W, H, Dmax, params, stream, &pl, &flags);
   if (rc) return rc;
   const int X = pl->X, Y = pl->Y, npix = X * Y;
-  if (!(flags & STEREO_SOFT_F_REUSE_FEATURES) || pl->feat_left != left || pl->feat_right != right)
+  const bool reuse = (flags & STEREO_SOFT_F_REUSE_FEATURES) != 0;
+  if (!reuse || pl->feat_left != left || pl->feat_right != right)
     soft_features(*pl, left, right, stream);
+  // the forward's weights of these inputs are on the plan: dL/dCA comes from
+  // them (k_soft_tcolw) instead of a recomputation of the aggregate
+  const bool saved = reuse && pl->wts_valid && pl->wts_left == left && pl->wts_right == right &&
+                     pl->wts_lam == lambdas;
   const float zc = (float)(std::ldexp(1.0, -pl->fxk) * 1.4426950408889634 / pl->p.tau);
   hipLaunchKernelGGL(k_soft_bprep, dim3((npix + 255) / 256, pl->n), dim3(256), 0, stream,
                      pl->inv_size, lse2, d_hat, g_dhat, npix, zc, 1.f / pl->p.tau, pl->pc);
   hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, stream, pl->g_half,
                      (size_t)2 * pl->n * npix, 0.f);
   const int groups = pl->nstrips * pl->nbands * pl->n;
+  const int tb = tcol_band(pl->p.arm_y);
+  if (!saved) pl->wts_valid = false;  // the slabs below overwrite the weight planes
   size_t lam_off = 0;
   for (int dlo = 0; dlo < pl->D; dlo += pl->nds) {
     const int dhi = std::min(pl->D, dlo + pl->nds), nds = dhi - dlo;
-    const int cs = best_chunk_size(groups, nds, pl->rows, c->num_cu);
-    launch_soft_agg<true>(*pl, soft_args(*pl, lambdas, dlo, dhi, cs), stream);
-    const int tb = pl->p.arm_y <= 31 ? kTcolBand : kTcolBand / 2;
-    hipLaunchKernelGGL(k_soft_tcol, dim3((X + 63) / 64, (Y + tb - 1) / tb, nds * pl->n),
-                       dim3(256), 0, stream, pl->gca, pl->arms, X, Y, pl->XA, pl->p.arm_y, pl->n,
-                       pl->gcax);
+    if (saved) {
+      // one slab holds all D; disparity groups so that the grid fills the
+      // CUs about four blocks deep
+      const int base = ((X + 63) / 64) * ((Y + tb - 1) / tb) * pl->n;
+      const int ndg = std::max(1, std::min(pl->D, (4 * c->num_cu + base - 1) / base));
+      hipLaunchKernelGGL(k_soft_tcolw, dim3((X + 63) / 64, (Y + tb - 1) / tb, pl->n * ndg),
+                         dim3(64 * kTcwWaves), 0, stream, pl->gca,
+                         (uint32_t)((size_t)pl->D * pl->n * npix * 4), pl->pc, pl->arms, X, Y,
+                         pl->XA, pl->p.arm_y, pl->n, pl->D, ndg, pl->gcax);
+    } else {
+      const int cs = best_chunk_size(groups, nds, pl->rows, c->num_cu);
+      launch_soft_agg<true>(*pl, soft_args(*pl, lambdas, dlo, dhi, cs), stream);
+      hipLaunchKernelGGL(k_soft_tcol, dim3((X + 63) / 64, (Y + tb - 1) / tb, nds * pl->n),
+                         dim3(256), 0, stream, pl->gca, pl->arms, X, Y, pl->XA, pl->p.arm_y,
+                         pl->n, pl->gcax);
+    }
     TrArgs ta{};
     ta.gcax = pl->gcax; ta.arms = pl->arms; ta.sp = pl->sp; ta.lam = lambdas;
     ta.g_half = pl->g_half; ta.gr_part = pl->gr_part;

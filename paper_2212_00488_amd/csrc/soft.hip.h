@@ -15,11 +15,15 @@
 //                           (1 - e^{-H/lambda_census}), CA over the cross
 //                           region, and the softmax sums over a d-chunk
 //             k_soft_merge  d_hat = sum d e_d / sum e_d, log2 sum e_d
+//             (with the weights saved, k_soft_agg also writes every e_d)
 //   backward  k_soft_bprep  per-pixel constants of dL/dCA
 //             k_soft_agg    (GCA mode) recomputes CA for a slab of d and
 //                           writes dL/dCA planes
 //             k_soft_tcol   transposed vertical window sums (integer difference
 //                           arrays over bands of output rows, LDS atomics)
+//             k_soft_tcolw  (weights saved by the forward) the same transpose
+//                           with dL/dCA formed from the saved e_d, in place of
+//                           k_soft_agg and k_soft_tcol
 //             k_soft_tr     transposed horizontal window sums back to dL/dC,
 //                           then dC/d(dI), dC/d(lambda) per pixel, summed over
 //                           the slab into the half-image gradients
@@ -145,6 +149,7 @@ struct SoftArgs {
   float2* part;             // [n][nchunk][Y][X] {sum e, sum d e}  (forward)
   const float4* pc;         // [n][Y][X] {w, log2 sum e, d_hat, A}  (GCA)
   float* gca;               // [nds][n][Y][X] dL/dCA           (GCA)
+  float* wts;               // [D][n][Y][X] e_d, or NULL        (forward)
   int X, Y, XS, pads, XA, arm_x, arm_y;
   int nbands, dlo, dhi, nstrips, ngroups, npair;
   int csize, nchunk;        // d-chunk size; chunks = ceil((dhi - dlo) / csize), the last the remainder
@@ -364,6 +369,9 @@ __global__ void __launch_bounds__(kThreads) k_soft_agg(SoftArgs a) {
           const float e = fast_exp2(-(float)ca * isz[k]);
           se[k] += e;
           sde[k] += fd * e;
+          const int r = o0 + wave + k * kWaves;
+          if (a.wts && x < X && r < o1)
+            a.wts[(size_t)d * a.npair * X * Y + ((size_t)pair * Y + ya + r) * X + x] = e;
         } else {
           const int r = o0 + wave + k * kWaves;
           const float4 q = qv[k % QB];
@@ -454,7 +462,7 @@ __global__ void __launch_bounds__(256) k_soft_bprep(const float* __restrict__ in
 constexpr int kTcolBand = 128;
 constexpr int kTcolSrc = 48;  // source rows per thread at most
 
-__device__ __forceinline__ int tcol_band(int arm_y) { return arm_y <= 31 ? kTcolBand : kTcolBand / 2; }
+__host__ __device__ constexpr int tcol_band(int arm_y) { return arm_y <= 31 ? kTcolBand : kTcolBand / 2; }
 
 __global__ void __launch_bounds__(256) k_soft_tcol(const float* __restrict__ gca,
                                                    const uint32_t* __restrict__ arms, int X,
@@ -529,6 +537,138 @@ __global__ void __launch_bounds__(256) k_soft_tcol(const float* __restrict__ gca
   for (int i = 0; i < kTcolBand / 4; ++i) {
     const int y = Y0 + r0 + i;
     if (i < rpw && y < Y1) out[(size_t)y * X] = (float)(loc[i] + off) * down;
+  }
+}
+
+// ------------------------------------------------------------ k_soft_tcolw
+// The transpose of k_soft_tcol with dL/dCA formed on the fly from the
+// softmax weights e_d = 2^{-CA(d) w} that the forward saved:
+//   dL/dCA(x,y,d) = A p_d (d - d_hat),  p_d = e_d 2^{-lse2}
+// (A, lse2 and d_hat from k_soft_bprep's constants), so the backward needs
+// neither k_soft_agg's recomputation of CA nor the dL/dCA planes.  A block
+// takes a 64-column strip, a band of B output rows (tcol_band) and a range
+// of disparities of one pair; thread (wave w, lane l) holds, over the range,
+// the constants and vertical arms of column x0 + l at the source rows
+// Y0 - arm_y + w + 8 i, and for each disparity builds the band's integer
+// difference array exactly as k_soft_tcol does (per-column power-of-two
+// scale from the largest |dL/dCA| of the band's sources, LDS integer atomics,
+// order-independent sums), then writes dL/dCA_x of the band's rows.
+// grid: (ceil(X/64), ceil(Y/B), n * ndg), block 512; disparity group g of
+// ndg covers [g D / ndg, (g + 1) D / ndg).
+constexpr int kTcwWaves = 16;
+constexpr int kTcwSrc = 12;  // source rows per thread: B + 2 arm_y <= 16 * 12
+static_assert(tcol_band(31) + 2 * 31 <= kTcwWaves * kTcwSrc &&
+                  tcol_band(63) + 2 * 63 <= kTcwWaves * kTcwSrc, "k_soft_tcolw source rows");
+
+__global__ void __launch_bounds__(64 * kTcwWaves) k_soft_tcolw(
+    const float* __restrict__ wts, uint32_t wts_bytes, const float4* __restrict__ pc,
+    const uint32_t* __restrict__ arms, int X, int Y, int XA, int arm_y, int npair, int D, int ndg,
+    float* __restrict__ gcax) {
+  __shared__ int s_d[kTcolBand + 1][64];
+  __shared__ float s_max[kTcwWaves][64];
+  __shared__ int s_tot[kTcwWaves][64];
+  const int lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int B = tcol_band(arm_y);
+  const int x = blockIdx.x * 64 + lane, Y0 = blockIdx.y * B;
+  const int pair = blockIdx.z % npair, dg = blockIdx.z / npair;
+  const int dlo = dg * D / ndg, dhi = (dg + 1) * D / ndg;
+  const int Y1 = min(Y, Y0 + B);
+  const bool xv = x < X;
+  const int xc = min(x, X - 1);
+  const size_t plane = (size_t)X * Y;
+  const int ys = max(0, Y0 - arm_y), ye = min(Y, Y1 + arm_y);
+  // source row of slot i (wave-uniform), clamped into the sources
+  auto src_row = [&](int i) { return min(ys + wave + kTcwWaves * i, ye - 1); };
+  // constants of the source rows ys + wave + 8 i (loads at clamped rows; a
+  // row outside the sources or a column past X gets A = 0, so it adds nothing)
+  float cA[kTcwSrc], cS[kTcwSrc], cD[kTcwSrc];
+  uint32_t cMN[kTcwSrc / 2];  // M | N << 8 of two rows, one per 16-bit half
+#pragma unroll
+  for (int i = 0; i < kTcwSrc; ++i) {
+    const int y = src_row(i);
+    const float4 q = pc[((size_t)pair * Y + y) * X + xc];
+    const uint32_t am = arms[((size_t)(2 * pair) * Y + y) * XA + xc] >> 16;
+    cA[i] = xv && ys + wave + kTcwWaves * i < ye ? q.w : 0.f;
+    cS[i] = fast_exp2(-q.y);
+    cD[i] = q.z;
+    if (i & 1) cMN[i / 2] |= am << 16;
+    else cMN[i / 2] = am;
+  }
+  // weight loads: the lane's column in the vector offset, the row and plane
+  // (wave-uniform) in the scalar one
+  const __amdgpu_buffer_rsrc_t rw = buffer_rsrc(wts, wts_bytes);
+  const uint32_t vcol = (uint32_t)xc * 4u;
+  const int rpw = B / kTcwWaves, r0 = wave * rpw;
+  // the weights of disparity d into w[]; the next disparity's are loaded
+  // while this one is processed (past the range: the last one again)
+  auto load_w = [&](int d, float (&w)[kTcwSrc]) {
+    const uint32_t sp = (uint32_t)(((size_t)min(d, dhi - 1) * npair + pair) * plane * 4);
+#pragma unroll
+    for (int i = 0; i < kTcwSrc; ++i)
+      w[i] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(
+          rw, vcol, sp + (uint32_t)src_row(i) * (uint32_t)X * 4u, 0));
+  };
+  float wn[kTcwSrc];
+  if (dlo < dhi) load_w(dlo, wn);
+  for (int d = dlo; d < dhi; ++d) {
+    const float fd = (float)d;
+    float g[kTcwSrc];
+#pragma unroll
+    for (int i = 0; i < kTcwSrc; ++i) g[i] = wn[i];
+    load_w(d + 1, wn);
+    float mx = 0.f;
+#pragma unroll
+    for (int i = 0; i < kTcwSrc; ++i) {
+      g[i] = cA[i] * (g[i] * cS[i]) * (fd - cD[i]);
+      mx = fmaxf(mx, fabsf(g[i]));
+    }
+    s_max[wave][lane] = mx;
+    for (int i = threadIdx.x; i < (B + 1) * 64; i += 64 * kTcwWaves) (&s_d[0][0])[i] = 0;
+    __syncthreads();
+    float cmax = 0.f;
+#pragma unroll
+    for (int w = 0; w < kTcwWaves; ++w) cmax = fmaxf(cmax, s_max[w][lane]);
+    int e = 0;
+    (void)frexpf(cmax, &e);
+    const float up = cmax > 0.f ? ldexpf(1.f, 23 - e) : 0.f;
+#pragma unroll
+    for (int i = 0; i < kTcwSrc; ++i) {
+      const int q = (int)rintf(g[i] * up);
+      if (q != 0) {
+        const int y = ys + wave + kTcwWaves * i;
+        const uint32_t mn = cMN[i / 2] >> (16 * (i & 1));
+        const int M = (int)(mn & 255u), N = (int)((mn >> 8) & 255u);
+        const int lo = max(y - M, Y0), hi = min(y + N, Y1 - 1);
+        if (lo <= hi) {
+          atomicAdd(&s_d[lo - Y0][lane], q);
+          if (hi + 1 < Y1) atomicAdd(&s_d[hi + 1 - Y0][lane], -q);
+        }
+      }
+    }
+    __syncthreads();
+    // prefix down the column: wave w takes rows w B/8 .. (w+1) B/8 - 1
+    int run = 0;
+    int loc[kTcolBand / kTcwWaves];
+#pragma unroll
+    for (int i = 0; i < kTcolBand / kTcwWaves; ++i) {
+      if (i < rpw) run += s_d[r0 + i][lane];
+      loc[i] = run;
+    }
+    s_tot[wave][lane] = run;
+    __syncthreads();
+    int off = 0;
+#pragma unroll
+    for (int w = 0; w < kTcwWaves - 1; ++w) off += w < wave ? s_tot[w][lane] : 0;
+    if (xv) {
+      const float down = cmax > 0.f ? ldexpf(1.f, e - 23) : 0.f;
+      float* out = gcax + ((size_t)d * npair + pair) * plane + x;
+#pragma unroll
+      for (int i = 0; i < kTcolBand / kTcwWaves; ++i) {
+        const int y = Y0 + r0 + i;
+        if (i < rpw && y < Y1) out[(size_t)y * X] = (float)(loc[i] + off) * down;
+      }
+    }
   }
 }
 

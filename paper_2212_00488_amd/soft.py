@@ -16,24 +16,29 @@ from __future__ import annotations
 
 import torch
 
-from .binding import SOFT_F_REUSE_FEATURES, SoftParams, soft_default_params
+from .binding import SOFT_F_REUSE_FEATURES, SOFT_F_SAVE_WEIGHTS, SoftParams, soft_default_params
+
+
+def _with_flags(params: SoftParams | None, flags: int) -> SoftParams:
+    p = soft_default_params() if params is None else SoftParams.from_buffer_copy(params)
+    p.flags |= flags
+    return p
 
 
 def _reusing(params: SoftParams | None) -> SoftParams:
     """params (defaults when None) with REUSE_FEATURES set: the backward
     gets the forward's saved inputs, which autograd keeps unchanged, so the
-    forward's features are reused whenever the plan still holds them (the
-    library checks that the last feature pass was for the same tensors)."""
-    p = soft_default_params() if params is None else SoftParams.from_buffer_copy(params)
-    p.flags |= SOFT_F_REUSE_FEATURES
-    return p
+    forward's features, and its softmax weights when it saved them, are
+    reused whenever the plan still holds them (the library checks that the
+    last forward was for the same tensors)."""
+    return _with_flags(params, SOFT_F_REUSE_FEATURES)
 
 
 class SoftArgmin(torch.autograd.Function):
     @staticmethod
-    def forward(fctx, left, right, lambdas, dmax, params, stereo):
+    def forward(fctx, left, right, lambdas, dmax, params, fwd_params, stereo):
         left, right, lambdas = left.contiguous(), right.contiguous(), lambdas.contiguous()
-        d_hat, lse2 = stereo.soft_forward(left, right, lambdas, dmax, params)
+        d_hat, lse2 = stereo.soft_forward(left, right, lambdas, dmax, fwd_params)
         fctx.save_for_backward(left, right, lambdas, d_hat, lse2)
         fctx.dmax, fctx.params, fctx.stereo = dmax, params, stereo
         fctx.mark_non_differentiable(lse2)
@@ -45,7 +50,7 @@ class SoftArgmin(torch.autograd.Function):
         g_left, g_right, g_lam = fctx.stereo.soft_backward(
             left, right, lambdas, fctx.dmax, d_hat, lse2, g_dhat.contiguous(),
             _reusing(fctx.params))
-        return g_left, g_right, g_lam, None, None, None
+        return g_left, g_right, g_lam, None, None, None, None
 
 
 class L1Loss(torch.autograd.Function):
@@ -64,8 +69,12 @@ class L1Loss(torch.autograd.Function):
 
 
 def soft_disparity(stereo, left, right, lambdas, dmax: int, params: SoftParams | None = None):
-    """Half-resolution soft-argmin disparity [n][Y][X] (differentiable)."""
-    d_hat, _ = SoftArgmin.apply(left, right, lambdas, dmax, params, stereo)
+    """Half-resolution soft-argmin disparity [n][Y][X] (differentiable).  When a
+    backward can follow (grad mode on and an input that requires grad), the
+    forward keeps its softmax weights for it (SAVE_WEIGHTS)."""
+    grad = torch.is_grad_enabled() and any(t.requires_grad for t in (left, right, lambdas))
+    fwd_params = _with_flags(params, SOFT_F_SAVE_WEIGHTS) if grad else params
+    d_hat, _ = SoftArgmin.apply(left, right, lambdas, dmax, params, fwd_params, stereo)
     return d_hat
 
 
