@@ -803,9 +803,14 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
     for (int i = 0; i < RPW; ++i) s_d[wave + 4 * i][lane] = 0;
     WAVE_LDS_ORDER();
     float down[RPW];
+    // sum of the terms whose window starts at or left of the strip's first
+    // column (all of them would add to entry 0: one wave sum instead of up to
+    // 64 atomics on one address), added to lane 0 before the row's scan
+    int qz[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
       const float g0 = cv[i][0] ? in.g[i][0] : 0.f, g1 = cv[i][1] ? in.g[i][1] : 0.f;
+      int qc = 0;
       const float mx = wave_max_f(fmaxf(fabsf(g0), fabsf(g1)));
       int e = 0;
       (void)frexpf(mx, &e);
@@ -820,11 +825,13 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
           const int lo = col - (int)(mv[i][h] & 255u) - x0;
           const int hi = col + (int)((mv[i][h] >> 8) & 255u) + 1 - x0;
           if (hi > 0 && lo < 64) {
-            atomicAdd(&s_d[wave + 4 * i][max(lo, 0)], q);
+            if (lo <= 0) qc += q;
+            else atomicAdd(&s_d[wave + 4 * i][lo], q);
             if (hi < 64) atomicAdd(&s_d[wave + 4 * i][hi], -q);
           }
         }
       }
+      qz[i] = (int)__builtin_amdgcn_readlane(wave_scan_incl((uint32_t)qc), 63);
     }
     WAVE_LDS_ORDER();
     // prefix along each row, then the cost derivatives; the right gradient
@@ -833,7 +840,8 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
       const int r = wave + 4 * i;
-      const float gc = (float)(int)wave_scan_incl((uint32_t)s_d[r][lane]) * down[i];
+      const int dz = s_d[r][lane] + (lane == 0 ? qz[i] : 0);
+      const float gc = (float)(int)wave_scan_incl((uint32_t)dz) * down[i];
       if (xin && dv && yv[i]) {
         const float di = __uint_as_float(pl_[i].x) - __uint_as_float(in.pr[i].x);
         const float ad = fabsf(di);
