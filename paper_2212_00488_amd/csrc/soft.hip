@@ -357,8 +357,11 @@ int stereo_soft_forward(stereo_ctx* c, const float* left, const float* right, in
   if (rc) return rc;
   soft_features(*pl, left, right, stream);
   SoftArgs a = soft_args(*pl, lambdas, 0, pl->D, pl->csize);
-  // the weights of all D fit the gca planes only when one slab covers D
-  pl->wts_valid = (flags & STEREO_SOFT_F_SAVE_WEIGHTS) && pl->nds >= pl->D;
+  // the weights of all D fit the gca planes only when one slab covers D;
+  // k_soft_tcolw addresses them through 32-bit buffer offsets
+  const size_t wts_bytes = (size_t)pl->D * pl->n * pl->X * pl->Y * 4;
+  pl->wts_valid = (flags & STEREO_SOFT_F_SAVE_WEIGHTS) && pl->nds >= pl->D &&
+                  wts_bytes < (size_t(1) << 32);
   if (pl->wts_valid) {
     a.wts = pl->gca;
     pl->wts_left = left;
