@@ -453,6 +453,9 @@ void launch_match_km(const Plan& pl, const MatchArgs& a, dim3 grid, hipStream_t 
   const int brows = pl.nbands == 1 ? pl.Y : std::min(pl.Y, (pl.Y + pl.nbands - 1) / pl.nbands + 2 * pl.p.arm_y);
   const int o0max = pl.nbands == 1 ? 0 : pl.p.arm_y;
   const int rows = std::max(brows, o0max + kWaves * KM) + 1;
+  // dynamic LDS beyond the default limit needs the attribute (set once per
+  // instance); were it refused, the launch below fails and run() reports
+  // that launch's error
   static const hipError_t attr = hipFuncSetAttribute(
       reinterpret_cast<const void*>(&k_match<NS, KM, DBG>),
       hipFuncAttributeMaxDynamicSharedMemorySize, kLdsBytes - kMatchTabBytes);
