@@ -422,22 +422,21 @@ def main():
 
     def frames(ns, k):
         """ms per frame of k frames issued round-robin on the first ns streams,
-        from an event before the first launch to one after the last frame."""
-        t0 = torch.cuda.Event(enable_timing=True)
-        t1 = torch.cuda.Event(enable_timing=True)
+        from the earliest of the events recorded on each stream before its
+        first launch to the latest of those recorded after its last frame (no
+        stream waits on another, so no cross-stream wait enters the interval)."""
         torch.cuda.synchronize()
-        t0.record(stream)
-        for s in side[:ns]:
-            s.wait_event(t0)
+        starts = [torch.cuda.Event(enable_timing=True) for _ in side[:ns]]
+        ends = [torch.cuda.Event(enable_timing=True) for _ in side[:ns]]
+        for e, s in zip(starts, side):
+            e.record(s)
         for i in range(k):
             ctx.disparity(left, right, DMAX, out=outs[i % ns], stream=side[i % ns])
-        for s in side[:ns]:
-            e = torch.cuda.Event()
+        for e, s in zip(ends, side):
             e.record(s)
-            stream.wait_event(e)
-        t1.record(stream)
         torch.cuda.synchronize()
-        return t0.elapsed_time(t1) / k
+        # max over (start, end) pairs of end - start = latest end - earliest start
+        return max(a.elapsed_time(b) for a in starts for b in ends) / k
 
     # warm-up: each stream's plan, then the launch stream's (stage times and
     # latency), one after the other
