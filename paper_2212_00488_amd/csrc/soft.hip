@@ -409,9 +409,10 @@ int stereo_soft_backward(stereo_ctx* c, const float* left, const float* right, i
     const int dhi = std::min(pl->D, dlo + pl->nds), nds = dhi - dlo;
     if (saved) {
       // one slab holds all D; disparity groups so that the grid fills the
-      // CUs about four blocks deep
+      // CUs about three blocks deep (each group reloads the per-pixel
+      // constants: at 4 x 718x496, 4 groups ran faster than 3 or 6)
       const int base = ((X + 63) / 64) * ((Y + tb - 1) / tb) * pl->n;
-      const int ndg = std::max(1, std::min(pl->D, (4 * c->num_cu + base - 1) / base));
+      const int ndg = std::max(1, std::min(pl->D, (3 * c->num_cu + base - 1) / base));
       hipLaunchKernelGGL(k_soft_tcolw, dim3((X + 63) / 64, (Y + tb - 1) / tb, pl->n * ndg),
                          dim3(64 * kTcwWaves), 0, stream, pl->gca,
                          (uint32_t)((size_t)pl->D * pl->n * npix * 4), pl->pc, pl->arms, X, Y,
