@@ -712,6 +712,18 @@ struct TrArgs {
   int X, Y, XS, pads, XA, npair, dlo, dhi, nstrips, nbands, WP;
 };
 
+// Inclusive maximum scan over the 64 lanes of a wave of values >= 0 (the
+// steps of wave_scan_incl; lanes a shift reaches past the row's start see 0).
+__device__ __forceinline__ int wave_max_scan_incl(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, false));  // row_shr:1
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, false));  // row_shr:2
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, false));  // row_shr:4
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, false));  // row_shr:8
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return v;
+}
+
 // Maximum over the 64 lanes of a wave, in every lane.
 __device__ __forceinline__ float wave_max_f(float v) {
   v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false)));  // row_ror:8
@@ -766,6 +778,30 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
     gl[i] = 0.f;
     for (int c = lane; c < kTrMaxWP; c += 64) s_gr[wave + 4 * i][c] = 0.f;
   }
+  // The two main updates of a row's difference array, -q at the right end
+  // hi of the sources left of the strip (h = 0) and +q at the left end lo of
+  // those right of it (h = 1), repeat a position over runs of neighbouring
+  // lanes whose arms stop at the same edge; such a run would serialise its
+  // atomics on one address.  The runs do not depend on d: per source and row,
+  // the lane where its run starts, whether it ends the run, and its position.
+  // Per d one wave scan gives each run's sum, added by the run's last lane.
+  uint32_t run[RPW][2];
+#pragma unroll
+  for (int i = 0; i < RPW; ++i) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int col = x0 - 32 + 64 * h + lane;
+      const int lo = col - (int)(mv[i][h] & 255u) - x0;
+      const int hi = col + (int)((mv[i][h] >> 8) & 255u) + 1 - x0;
+      const bool part = cv[i][h] && (h == 0 ? hi > 0 : lo < 64);
+      const int pos = h == 0 ? hi : lo;
+      const int key = part ? pos : -1 - lane;
+      const int kp = __builtin_amdgcn_update_dpp(1000, key, 0x138, 0xf, 0xf, false);  // wave_shr:1
+      const int kn = __builtin_amdgcn_update_dpp(1000, key, 0x130, 0xf, 0xf, false);  // wave_shl:1
+      const int hs = wave_max_scan_incl(key != kp ? lane : 0);
+      run[i][h] = (uint32_t)hs | (part && key != kn ? 256u : 0u) | (uint32_t)(pos & 63) << 9;
+    }
+  }
   const float lam_ad = a.lam[0], lam_c = a.lam[1];
   const float k2 = 255.f * 1.4426950408889634f / lam_ad;
   const float kt = 255.f / lam_ad, ka = 1.f / (lam_ad * lam_ad), kc = 1.f / (lam_c * lam_c);
@@ -816,6 +852,7 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
       (void)frexpf(mx, &e);
       const float up = mx > 0.f ? ldexpf(1.f, 23 - e) : 0.f;
       down[i] = mx > 0.f ? ldexpf(1.f, e - 23) : 0.f;
+      int vr[2] = {0, 0};  // this lane's term of the run update of h = 0, 1
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const float gvh = h ? g1 : g0;
@@ -825,11 +862,24 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
           const int lo = col - (int)(mv[i][h] & 255u) - x0;
           const int hi = col + (int)((mv[i][h] >> 8) & 255u) + 1 - x0;
           if (hi > 0 && lo < 64) {
-            if (lo <= 0) qc += q;
-            else atomicAdd(&s_d[wave + 4 * i][lo], q);
-            if (hi < 64) atomicAdd(&s_d[wave + 4 * i][hi], -q);
+            if (h == 0) {
+              vr[0] = -q;  // at hi (always < 64 here)
+              if (lo <= 0) qc += q;
+              else atomicAdd(&s_d[wave + 4 * i][lo], q);
+            } else {
+              vr[1] = q;   // at lo (always >= 1 here)
+              if (hi < 64) atomicAdd(&s_d[wave + 4 * i][hi], -q);
+            }
           }
         }
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int P = (int)wave_scan_incl((uint32_t)vr[h]);
+        const int hs = (int)(run[i][h] & 255u);
+        const int Pm = __builtin_amdgcn_ds_bpermute(max(hs - 1, 0) * 4, P);
+        if (run[i][h] & 256u)
+          atomicAdd(&s_d[wave + 4 * i][run[i][h] >> 9], P - (hs > 0 ? Pm : 0));
       }
       qz[i] = (int)__builtin_amdgcn_readlane(wave_scan_incl((uint32_t)qc), 63);
     }
