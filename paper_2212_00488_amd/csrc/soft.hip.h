@@ -971,29 +971,36 @@ __global__ void __launch_bounds__(256) k_soft_gright(const float* __restrict__ g
 __global__ void __launch_bounds__(256) k_soft_gfull(const float* __restrict__ g_half, int W, int H,
                                                     int X, int Y, float* __restrict__ g_left,
                                                     float* __restrict__ g_right) {
-  const int u = blockIdx.x * 256 + threadIdx.x, v = blockIdx.y, img = blockIdx.z;
-  if (u >= W) return;
-  const float* gh = g_half + (size_t)img * X * Y;
-  float acc = 0.f;
-  const int yl = max(0, (v - 1) >> 1), yh = min(Y - 1, (v + 2) >> 1);
-  const int xl = max(0, (u - 1) >> 1), xh = min(X - 1, (u + 2) >> 1);
-  for (int y = yl; y <= yh; ++y) {
-    int wy = 0;
+  __shared__ float s_o[256 * 3];
+  const int u0 = blockIdx.x * 256, u = u0 + threadIdx.x, v = blockIdx.y, img = blockIdx.z;
+  if (u < W) {
+    const float* gh = g_half + (size_t)img * X * Y;
+    float acc = 0.f;
+    const int yl = max(0, (v - 1) >> 1), yh = min(Y - 1, (v + 2) >> 1);
+    const int xl = max(0, (u - 1) >> 1), xh = min(X - 1, (u + 2) >> 1);
+    for (int y = yl; y <= yh; ++y) {
+      int wy = 0;
 #pragma unroll
-    for (int j = -1; j <= 1; ++j) wy += clampi(2 * y + j, 0, H - 1) == v;
-    if (!wy) continue;
-    for (int x = xl; x <= xh; ++x) {
-      int wx = 0;
+      for (int j = -1; j <= 1; ++j) wy += clampi(2 * y + j, 0, H - 1) == v;
+      if (!wy) continue;
+      for (int x = xl; x <= xh; ++x) {
+        int wx = 0;
 #pragma unroll
-      for (int i = -1; i <= 1; ++i) wx += clampi(2 * x + i, 0, W - 1) == u;
-      if (wx) acc += (float)(wx * wy) * gh[(size_t)y * X + x];
+        for (int i = -1; i <= 1; ++i) wx += clampi(2 * x + i, 0, W - 1) == u;
+        if (wx) acc += (float)(wx * wy) * gh[(size_t)y * X + x];
+      }
     }
+    acc *= 1.f / (9.f * 256.f);
+    s_o[3 * threadIdx.x] = 77.f * acc;
+    s_o[3 * threadIdx.x + 1] = 150.f * acc;
+    s_o[3 * threadIdx.x + 2] = 29.f * acc;
   }
-  acc *= 1.f / (9.f * 256.f);
-  float* out = ((img & 1) ? g_right : g_left) + ((size_t)(img >> 1) * H * W + (size_t)v * W + u) * 3;
-  out[0] = 77.f * acc;
-  out[1] = 150.f * acc;
-  out[2] = 29.f * acc;
+  __syncthreads();
+  // the block's 3 nu consecutive floats of the row, consecutive threads on
+  // consecutive floats
+  float* row = ((img & 1) ? g_right : g_left) + ((size_t)(img >> 1) * H * W + (size_t)v * W) * 3;
+  const int nu = min(256, W - u0);
+  for (int k = threadIdx.x; k < 3 * nu; k += 256) row[(size_t)u0 * 3 + k] = s_o[k];
 }
 
 // ------------------------------------------------------------ k_soft_lam
@@ -1056,12 +1063,15 @@ __global__ void __launch_bounds__(256) k_l1_partial(const float* __restrict__ dh
   const int t = threadIdx.x, pair = blockIdx.y;
   const int npix = X * Y;
   float sum = 0.f, cnt = 0.f;
-  for (int i = blockIdx.x * 256 + t; i < npix; i += gridDim.x * 256) {
-    const int y = i / X, x = i - y * X;
-    const size_t f = (size_t)pair * H * W + (size_t)(2 * y) * W + 2 * x;
-    if (nonocc[f]) {
-      sum += fabsf(2.f * dhat[(size_t)pair * npix + i] - (float)gt[f]);
-      cnt += 1.f;
+  // block b takes the rows b, b + nblk, ...; its threads the columns
+  for (int y = blockIdx.x; y < Y; y += gridDim.x) {
+    const size_t fr = (size_t)pair * H * W + (size_t)(2 * y) * W;
+    const float* dr = dhat + (size_t)pair * npix + (size_t)y * X;
+    for (int x = t; x < X; x += 256) {
+      if (nonocc[fr + 2 * x]) {
+        sum += fabsf(2.f * dr[x] - (float)gt[fr + 2 * x]);
+        cnt += 1.f;
+      }
     }
   }
   s[t] = make_float2(sum, cnt);
@@ -1076,22 +1086,29 @@ __global__ void __launch_bounds__(256) k_l1_partial(const float* __restrict__ dh
   if (t == 0) part[(size_t)pair * gridDim.x + blockIdx.x] = s[0];
 }
 
-// k_l1_final grid: 1, block 64: loss and the per-pair counts.
+// k_l1_final grid: 1, block 64: loss and the per-pair counts.  Lane b sums
+// the blocks b, b + 64, ... of a pair, then a butterfly over the lanes (a
+// fixed order: the result does not depend on scheduling).
 __global__ void __launch_bounds__(64) k_l1_final(const float2* __restrict__ part, int nblk,
                                                  int npair, float* __restrict__ loss,
                                                  float* __restrict__ counts) {
-  if (threadIdx.x != 0) return;
+  const int lane = threadIdx.x;
   float total = 0.f;
   for (int p = 0; p < npair; ++p) {
     float s = 0.f, c = 0.f;
-    for (int b = 0; b < nblk; ++b) {
+    for (int b = lane; b < nblk; b += 64) {
       s += part[(size_t)p * nblk + b].x;
       c += part[(size_t)p * nblk + b].y;
     }
-    counts[p] = c;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      s += __shfl_xor(s, o, 64);
+      c += __shfl_xor(c, o, 64);
+    }
+    if (lane == 0) counts[p] = c;
     total += s / fmaxf(c, 1.f);
   }
-  *loss = total / (float)npair;
+  if (lane == 0) *loss = total / (float)npair;
 }
 
 // k_l1_grad grid: (ceil(X*Y/256), n), block 256.
