@@ -971,36 +971,29 @@ __global__ void __launch_bounds__(256) k_soft_gright(const float* __restrict__ g
 __global__ void __launch_bounds__(256) k_soft_gfull(const float* __restrict__ g_half, int W, int H,
                                                     int X, int Y, float* __restrict__ g_left,
                                                     float* __restrict__ g_right) {
-  __shared__ float s_o[256 * 3];
-  const int u0 = blockIdx.x * 256, u = u0 + threadIdx.x, v = blockIdx.y, img = blockIdx.z;
-  if (u < W) {
-    const float* gh = g_half + (size_t)img * X * Y;
-    float acc = 0.f;
-    const int yl = max(0, (v - 1) >> 1), yh = min(Y - 1, (v + 2) >> 1);
-    const int xl = max(0, (u - 1) >> 1), xh = min(X - 1, (u + 2) >> 1);
-    for (int y = yl; y <= yh; ++y) {
-      int wy = 0;
+  const int u = blockIdx.x * 256 + threadIdx.x, v = blockIdx.y, img = blockIdx.z;
+  if (u >= W) return;
+  const float* gh = g_half + (size_t)img * X * Y;
+  float acc = 0.f;
+  const int yl = max(0, (v - 1) >> 1), yh = min(Y - 1, (v + 2) >> 1);
+  const int xl = max(0, (u - 1) >> 1), xh = min(X - 1, (u + 2) >> 1);
+  for (int y = yl; y <= yh; ++y) {
+    int wy = 0;
 #pragma unroll
-      for (int j = -1; j <= 1; ++j) wy += clampi(2 * y + j, 0, H - 1) == v;
-      if (!wy) continue;
-      for (int x = xl; x <= xh; ++x) {
-        int wx = 0;
+    for (int j = -1; j <= 1; ++j) wy += clampi(2 * y + j, 0, H - 1) == v;
+    if (!wy) continue;
+    for (int x = xl; x <= xh; ++x) {
+      int wx = 0;
 #pragma unroll
-        for (int i = -1; i <= 1; ++i) wx += clampi(2 * x + i, 0, W - 1) == u;
-        if (wx) acc += (float)(wx * wy) * gh[(size_t)y * X + x];
-      }
+      for (int i = -1; i <= 1; ++i) wx += clampi(2 * x + i, 0, W - 1) == u;
+      if (wx) acc += (float)(wx * wy) * gh[(size_t)y * X + x];
     }
-    acc *= 1.f / (9.f * 256.f);
-    s_o[3 * threadIdx.x] = 77.f * acc;
-    s_o[3 * threadIdx.x + 1] = 150.f * acc;
-    s_o[3 * threadIdx.x + 2] = 29.f * acc;
   }
-  __syncthreads();
-  // the block's 3 nu consecutive floats of the row, consecutive threads on
-  // consecutive floats
-  float* row = ((img & 1) ? g_right : g_left) + ((size_t)(img >> 1) * H * W + (size_t)v * W) * 3;
-  const int nu = min(256, W - u0);
-  for (int k = threadIdx.x; k < 3 * nu; k += 256) row[(size_t)u0 * 3 + k] = s_o[k];
+  acc *= 1.f / (9.f * 256.f);
+  float* out = ((img & 1) ? g_right : g_left) + ((size_t)(img >> 1) * H * W + (size_t)v * W + u) * 3;
+  out[0] = 77.f * acc;
+  out[1] = 150.f * acc;
+  out[2] = 29.f * acc;
 }
 
 // ------------------------------------------------------------ k_soft_lam

@@ -42,11 +42,15 @@ class SoftArgmin(torch.autograd.Function):
         fctx.save_for_backward(left, right, lambdas, d_hat, lse2)
         fctx.dmax, fctx.params, fctx.stereo = dmax, params, stereo
         fctx.mark_non_differentiable(lse2)
+        # lse2 takes no gradient: no zero tensor is made for it
+        fctx.set_materialize_grads(False)
         return d_hat, lse2
 
     @staticmethod
     def backward(fctx, g_dhat, _g_lse):
         left, right, lambdas, d_hat, lse2 = fctx.saved_tensors
+        if g_dhat is None:  # nothing flows back (possible without materialised grads)
+            return None, None, None, None, None, None, None
         g_left, g_right, g_lam = fctx.stereo.soft_backward(
             left, right, lambdas, fctx.dmax, d_hat, lse2, g_dhat.contiguous(),
             _reusing(fctx.params))
