@@ -166,46 +166,65 @@ constexpr int kMaxArm = 127;
 // arm cap: arm + 1, rounded up to even (the row pass takes column pairs).
 __host__ __device__ constexpr int row_halo(int arm_cap) { return (arm_cap + 2) & ~1; }
 
+// Keeps the compiler from moving LDS accesses of one wave across this point;
+// the LDS itself serves the accesses of a wave in issue order.
+#define WAVE_LDS_ORDER() __asm__ volatile("" ::: "memory")
+
 // Length of one arm of a pixel of value c: the number of steps t = 1, 2, ...
 // along the axis, taken without a break, whose pixel satisfies |I - c| < delta,
 // at most lim.  p points at the pixel in an LDS tile and STRIDE is the tile
 // distance of one step (negative for the left / upper arm).  Steps are tested
-// in chunks of 32 into a bitmask, step t of a chunk in bit t-1, built from the
-// farthest step down so that each test is one add-with-carry; the chunk's run
-// is the number of trailing ones.  Steps are tested 4 at a time, so up to 3
-// steps past the cap are tested too: they only set bits above the cap, which
-// lim (<= cap) cuts off, and the tile holds kArmPad spare pixels for them.
-constexpr int kArmPad = 3;
+// in chunks of up to 32 into a bitmask of the steps that fail, step t of a
+// chunk in bit t-1, built from the farthest step down; the chunk's run is the
+// number of trailing zeros.  A test is two VALU ops: v_sad_u16 forms
+// |v - c| + 2^31 - delta, whose bit 31 is [|v - c| >= delta], and
+// v_alignbit_b32 shifts that bit into the mask.  A chunk's loads are all
+// issued before its first test.  The last chunk tests the cap rounded up to a
+// multiple of 8 steps (a wave-uniform choice among four unrolled forms): the
+// steps past the cap only set bits above it, which lim (<= cap) cuts off, and
+// the tile holds kArmPad spare pixels for them.
+constexpr int kArmPad = 7;
 
-// m * 2 + [x < w]: the compare's lane bit enters as the carry of m + m
-__device__ __forceinline__ uint32_t shift_in_lt(uint32_t m, uint32_t x, uint32_t w) {
-  uint32_t r;
-  __asm__("v_cmp_gt_u32_e32 vcc, %2, %1\n\tv_addc_co_u32_e32 %0, vcc, %3, %3, vcc"
-          : "=v"(r) : "v"(x), "s"(w), "v"(m) : "vcc");
-  return r;
+// Run of passing steps 1..N (N <= 32) from p, bias = 2^31 - delta.
+template <int STRIDE, int N>
+__device__ __forceinline__ int arm_run(const uint8_t* p, uint32_t c, uint32_t bias) {
+  // one byte load per step (merged into wide loads, each byte would take
+  // one more VALU op to extract; the compiler barrier keeps them apart)
+  uint32_t v[N];
+#pragma unroll
+  for (int t = 1; t <= N; ++t) {
+    v[t - 1] = p[t * STRIDE];
+    WAVE_LDS_ORDER();
+  }
+  // the bits above N - 1 start as failures, so a chunk of fewer than 32
+  // steps ends its run at N at most
+  uint32_t m = 0xffffffffu;
+#pragma unroll
+  for (int t = N; t >= 1; --t)
+    m = __builtin_amdgcn_alignbit(m, __builtin_amdgcn_sad_u16(v[t - 1], c, bias), 31);
+  return m == 0u ? 32 : __builtin_ctz(m);
 }
 
 template <int STRIDE>
 __device__ __forceinline__ int arm_len(const uint8_t* p, int c, int delta, int cap, int lim) {
-  if (delta <= 0) return 0;
-  // |v - c| < delta  <=>  (unsigned)(v + k) < w
-  uint32_t k = (uint32_t)(delta - 1 - c);
-  __asm__ volatile("" : "+v"(k));  // one per-lane operand: the test is add, compare
-  const unsigned w = 2u * (unsigned)delta - 1u;
+  if (delta <= 0 || cap <= 0) return 0;
+  const uint32_t bias = 0x80000000u - (uint32_t)delta;
+  const uint32_t cu = (uint32_t)c;
   int len = 0;
   bool alive = true;
-  for (int c0 = 0; c0 < cap; c0 += 32) {
-    const int n4 = (min(32, cap - c0) + 3) & ~3;
-    uint32_t m = 0;
-    for (int u = n4; u > 0; u -= 4) {
-      const uint8_t* q = p + (c0 + u) * STRIDE;  // step c0 + u, then three nearer ones
-#pragma unroll
-      for (int j = 0; j < 4; ++j) m = shift_in_lt(m, (uint32_t)q[-j * STRIDE] + k, w);
-    }
-    const int run = m == 0xffffffffu ? 32 : __builtin_ctz(~m);
+  for (; cap > 32; cap -= 32, p += 32 * STRIDE) {
+    const int run = arm_run<STRIDE, 32>(p, cu, bias);
     len += alive ? run : 0;
     alive = alive && run == 32;
   }
+  int run;
+  switch ((cap + 7) >> 3) {
+    case 1: run = arm_run<STRIDE, 8>(p, cu, bias); break;
+    case 2: run = arm_run<STRIDE, 16>(p, cu, bias); break;
+    case 3: run = arm_run<STRIDE, 24>(p, cu, bias); break;
+    default: run = arm_run<STRIDE, 32>(p, cu, bias); break;
+  }
+  len += alive ? run : 0;
   return min(len, lim);
 }
 
@@ -243,13 +262,60 @@ k_feat(const uint8_t* __restrict__ half, int X, int Y, int delta, int arm_x_l, i
   // tile margins: the arms plus the spare steps (at least the census's 2)
   const int hx = arm_x + kArmPad, wx = 64 + 2 * hx;
   const int my = arm_y + kArmPad, hy = kFeatRows + 2 * my;
-  for (int r = threadIdx.y; r < kFeatRows + 2; r += kFeatRows) {
-    const uint8_t* src = h + (size_t)clampi(y0 - 1 + r, 0, Y - 1) * X;
-    for (int c = threadIdx.x; c < wx; c += 64) tx[r][c] = src[clampi(x0 - hx + c, 0, X - 1)];
+  // Tile loads: the loads of both tiles' first batches are issued before
+  // the first store (one load, wait and store after another was bound by
+  // memory latency); larger caps take more batches.  Rows and columns past a
+  // tile's end are clamped to its last one: such a load and store repeat a
+  // valid one with the same value.
+  {
+    const int r0 = (int)threadIdx.y, r1 = min(r0 + kFeatRows, kFeatRows + 1);
+    const uint8_t* s0 = h + (size_t)clampi(y0 - 1 + r0, 0, Y - 1) * X;
+    const uint8_t* s1 = h + (size_t)clampi(y0 - 1 + r1, 0, Y - 1) * X;
+    const uint8_t* sc = h + clampi(x0 + (int)threadIdx.x, 0, X - 1);
+    // tx: rows r0, r1 and columns c0 + lane, c0 + 64 + lane
+    auto load_x = [&](int c0, int* cc, uint8_t* v) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        cc[k] = min(c0 + 64 * k + (int)threadIdx.x, wx - 1);
+        const int gx = clampi(x0 - hx + cc[k], 0, X - 1);
+        v[2 * k] = s0[gx];
+        v[2 * k + 1] = s1[gx];
+      }
+    };
+    auto store_x = [&](const int* cc, const uint8_t* v) {
+#pragma unroll
+      for (int k = 0; k < 2; ++k) {
+        tx[r0][cc[k]] = v[2 * k];
+        tx[r1][cc[k]] = v[2 * k + 1];
+      }
+    };
+    // ty: rows (j0 + j) * kFeatRows + r0, j < 8, of column lane
+    auto load_y = [&](int j0, int* rr, uint8_t* v) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        rr[j] = min((j0 + j) * kFeatRows + r0, hy - 1);
+        v[j] = sc[(size_t)clampi(y0 - my + rr[j], 0, Y - 1) * X];
+      }
+    };
+    auto store_y = [&](const int* rr, const uint8_t* v) {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) ty[rr[j]][threadIdx.x] = v[j];
+    };
+    int cc[2], rr[8];
+    uint8_t vx[4], vy[8];
+    load_x(0, cc, vx);
+    load_y(0, rr, vy);
+    store_x(cc, vx);
+    store_y(rr, vy);
+    for (int c0 = 128; c0 < wx; c0 += 128) {
+      load_x(c0, cc, vx);
+      store_x(cc, vx);
+    }
+    for (int j0 = 8; j0 * kFeatRows < hy; j0 += 8) {
+      load_y(j0, rr, vy);
+      store_y(rr, vy);
+    }
   }
-  const int cx = clampi(x0 + (int)threadIdx.x, 0, X - 1);
-  for (int r = threadIdx.y; r < hy; r += kFeatRows)
-    ty[r][threadIdx.x] = h[(size_t)clampi(y0 - my + r, 0, Y - 1) * X + cx];
   __syncthreads();
   const int lx = threadIdx.x, x = x0 + lx, ly = threadIdx.y, y = y0 + ly;
   const bool inside = x < X && y < Y;
@@ -311,9 +377,6 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
   return v;
 }
 
-// Keeps the compiler from moving LDS accesses of one wave across this point;
-// the LDS itself serves the accesses of a wave in issue order.
-#define WAVE_LDS_ORDER() __asm__ volatile("" ::: "memory")
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
