@@ -166,10 +166,6 @@ constexpr int kMaxArm = 127;
 // arm cap: arm + 1, rounded up to even (the row pass takes column pairs).
 __host__ __device__ constexpr int row_halo(int arm_cap) { return (arm_cap + 2) & ~1; }
 
-// Keeps the compiler from moving LDS accesses of one wave across this point;
-// the LDS itself serves the accesses of a wave in issue order.
-#define WAVE_LDS_ORDER() __asm__ volatile("" ::: "memory")
-
 // Length of one arm of a pixel of value c: the number of steps t = 1, 2, ...
 // along the axis, taken without a break, whose pixel satisfies |I - c| < delta,
 // at most lim.  p points at the pixel in an LDS tile and STRIDE is the tile
@@ -194,7 +190,7 @@ __device__ __forceinline__ int arm_run(const uint8_t* p, uint32_t c, uint32_t bi
 #pragma unroll
   for (int t = 1; t <= N; ++t) {
     v[t - 1] = p[t * STRIDE];
-    WAVE_LDS_ORDER();
+    __asm__ volatile("" ::: "memory");
   }
   // the bits above N - 1 start as failures, so a chunk of fewer than 32
   // steps ends its run at N at most
@@ -377,6 +373,10 @@ __device__ __forceinline__ uint32_t wave_scan_incl(uint32_t v) {
   return v;
 }
 
+
+// Keeps the compiler from moving LDS accesses of one wave across this point;
+// the LDS itself serves the accesses of a wave in issue order.
+#define WAVE_LDS_ORDER() __asm__ volatile("" ::: "memory")
 
 typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 
