@@ -152,8 +152,8 @@ __global__ void __launch_bounds__(256) k_prep(PairPtrs pp, int W, int H, int X, 
 }
 
 // ---------------------------------------------------------------- k_feat
-// Packed half-res pixels.  The differentiable head takes gray * 2 in bits
-// 0..9 and the census string in bits 16..21 (32 bits).  k_match takes gray in
+// Packed half-res pixels.  The differentiable head takes {the float half
+// image value's bits, census string} (8 bytes).  k_match takes gray in
 // bits 0..7 and the census string in bits 8..13 (16 bits), two pixels per
 // 32-bit load; that plane is stored twice, the second copy one pixel to the
 // right, so that the pair of pixels starting at any column is one aligned
@@ -232,9 +232,10 @@ __device__ __forceinline__ int arm_len(const uint8_t* p, int c, int delta, int c
 //   census: 6 neighbours in three rows, bit k = [neighbour < centre]
 //   arms  : contiguous pixels with |I - I(centre)| < delta, capped per side
 //           and at the image border; packed m | n<<8 | M<<16 | N<<24
-// Pixels go to pk (gray * 2 | census << 16, may be NULL) and to the two copies
-// of pk16 (gray | census << 8, may be NULL; the second copy copy16 elements
-// after the first, one pixel to the right); pitch XP, column x at pad + x.
+// Pixels go to sp ({bits of half_f at the pixel (an unpadded [Y][X] plane per
+// image), census}, may be NULL) and to the two copies of pk16 (gray | census
+// << 8, may be NULL; the second copy copy16 elements after the first, one
+// pixel to the right); pitch XP, column x at pad + x.
 // xoff (may be NULL) takes, for k_match's row pass, the byte offsets in a
 // wave's row buffer of the row-prefix entries that bound CA_x (Eq. 7) at x:
 // 4 (x mod 64 + h - m - 1) in bits 0..15 and 4 (x mod 64 + h + n) in bits
@@ -245,9 +246,9 @@ __device__ __forceinline__ int arm_len(const uint8_t* p, int c, int delta, int c
 // grid: (ceil(X/64), ceil(Y/kFeatRows), 2 * npair), block (64, kFeatRows).
 __global__ void __launch_bounds__(64 * kFeatRows) __attribute__((amdgpu_waves_per_eu(8)))
 k_feat(const uint8_t* __restrict__ half, int X, int Y, int delta, int arm_x_l, int arm_x_r,
-       int arm_y, int XP, int pad, int XA, uint32_t* __restrict__ pk,
-       uint32_t* __restrict__ arms, uint32_t* __restrict__ xoff, uint16_t* __restrict__ pk16,
-       size_t copy16) {
+       int arm_y, int XP, int pad, int XA, const float* __restrict__ half_f,
+       uint2* __restrict__ sp, uint32_t* __restrict__ arms, uint32_t* __restrict__ xoff,
+       uint16_t* __restrict__ pk16, size_t copy16) {
   constexpr int TXW = 64 + 2 * (kMaxArm + kArmPad);
   __shared__ uint8_t tx[kFeatRows + 2][TXW];
   __shared__ uint8_t ty[kFeatRows + 2 * (kMaxArm + kArmPad)][64];
@@ -331,7 +332,9 @@ k_feat(const uint8_t* __restrict__ half, int X, int Y, int delta, int arm_x_l, i
     const int n = arm_len<1>(row, c, delta, arm_x, min(arm_x, X - 1 - x));
     const int M = arm_len<-64>(col, c, delta, arm_y, min(arm_y, y));
     const int N = arm_len<64>(col, c, delta, arm_y, min(arm_y, Y - 1 - y));
-    if (pk) pk[((size_t)img * Y + y) * XP + pad + x] = (uint32_t)(2 * c) | ((uint32_t)bits << 16);
+    if (sp)
+      sp[((size_t)img * Y + y) * XP + pad + x] =
+          make_uint2(__float_as_uint(half_f[((size_t)img * Y + y) * X + x]), (uint32_t)bits);
     arms[((size_t)img * Y + y) * XA + x] =
         (uint32_t)m | ((uint32_t)n << 8) | ((uint32_t)M << 16) | ((uint32_t)N << 24);
     if (xoff) {

@@ -33,7 +33,6 @@ struct SoftPlan {
   void* block = nullptr;
   float* half_f = nullptr;     // [2n][Y][X]
   uint8_t* half_u8 = nullptr;  // [2n][Y][X]
-  uint32_t* pk = nullptr;      // [2n][Y][X]  census << 16 (k_feat, unpadded)
   uint32_t* arms = nullptr;    // [2n][Y][XA]
   uint2* sp = nullptr;         // [2n][Y][XS] padded {half value, census}
   float* inv_size = nullptr;   // [n][Y][X]
@@ -156,7 +155,7 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
     return fail(c, STEREO_EINVAL, "%d pairs of %dx%d exceed the 4 GiB pixel or arm planes of the "
                 "soft head; pass fewer pairs per call", n, W, H);
   }
-  size_t bytes = al(nimg * npix * 4) + al(nimg * npix) + al(nimg * npix * 4) +
+  size_t bytes = al(nimg * npix * 4) + al(nimg * npix) +
                  al(nimg * Y * pl->XA * 4) + al(nimg * Y * pl->XS * 8) + al(n * npix * 4) +
                  al((size_t)n * pl->nchunk * npix * 8) + al(n * npix * 16) +
                  2 * al((size_t)pl->nds * n * npix * 4) + al(nimg * npix * 4) +
@@ -176,7 +175,6 @@ int make_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_so
   char* cur = static_cast<char*>(pl->block);
   pl->half_f = carve<float>(cur, nimg * npix);
   pl->half_u8 = carve<uint8_t>(cur, nimg * npix);
-  pl->pk = carve<uint32_t>(cur, nimg * npix);
   pl->arms = carve<uint32_t>(cur, nimg * Y * pl->XA);
   pl->sp = carve<uint2>(cur, nimg * Y * pl->XS);
   pl->inv_size = carve<float>(cur, n * npix);
@@ -230,7 +228,8 @@ int get_soft_plan(stereo_ctx* c, int n, int W, int H, int Dmax, const stereo_sof
 }
 
 // Features shared by forward and backward: float and uint8 half images,
-// census and arms (k_feat of the integer path), padded pixel planes, 1/|S|.
+// census and arms (k_feat of the integer path, which also writes the padded
+// pixel planes), 1/|S|.
 void soft_features(SoftPlan& pl, const float* left, const float* right, hipStream_t s) {
   pl.feat_left = left;
   pl.feat_right = right;
@@ -239,9 +238,8 @@ void soft_features(SoftPlan& pl, const float* left, const float* right, hipStrea
                      right, pl.W, pl.H, X, Y, pl.half_f, pl.half_u8);
   hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + kFeatRows - 1) / kFeatRows, n2),
                      dim3(64, kFeatRows), 0, s, pl.half_u8, X, Y, pl.p.color_delta, pl.p.arm_x,
-                     pl.p.arm_x, pl.p.arm_y, X, 0, pl.XA, pl.pk, pl.arms, nullptr, nullptr, 0);
-  hipLaunchKernelGGL(k_soft_pack, dim3((X + 255) / 256, Y, n2), dim3(256), 0, s, pl.half_f, pl.pk,
-                     X, Y, pl.XS, pl.pads, pl.sp);
+                     pl.p.arm_x, pl.p.arm_y, pl.XS, pl.pads, pl.XA, pl.half_f, pl.sp, pl.arms,
+                     nullptr, nullptr, 0);
   hipLaunchKernelGGL(k_soft_size, dim3((X + 63) / 64, (Y + kSizeRows - 1) / kSizeRows, pl.n),
                      dim3(64, kSizeRows), 0, s, pl.arms, X, Y, pl.XA, pl.p.arm_y, pl.inv_size);
 }
@@ -286,7 +284,7 @@ int launch_status(stereo_ctx* c) {
   return 0;
 }
 
-constexpr int kL1Blocks = 64;  // partial-sum blocks per pair
+constexpr int kL1Blocks = 256;  // partial-sum blocks per pair
 
 // L1 scratch of the context for the stream s: partials [kSoftMaxPairs][kL1Blocks],
 // counts [kSoftMaxPairs], loss [1]; one block per stream (made on first use),
@@ -324,7 +322,7 @@ void l1_reduce(int n, int W, int H, const float* d_hat, const int16_t* gt, const
   const int X = (W + 1) / 2, Y = (H + 1) / 2;
   hipLaunchKernelGGL(k_l1_partial, dim3(kL1Blocks, n), dim3(256), 0, s, d_hat, gt, nonocc, W, H,
                      X, Y, part);
-  hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(64), 0, s, part, kL1Blocks, n, loss, counts);
+  hipLaunchKernelGGL(k_l1_final, dim3(1), dim3(256), 0, s, part, kL1Blocks, n, loss, counts);
 }
 
 }  // namespace stereo_host
@@ -399,8 +397,6 @@ int stereo_soft_backward(stereo_ctx* c, const float* left, const float* right, i
   const float zc = (float)(std::ldexp(1.0, -pl->fxk) * 1.4426950408889634 / pl->p.tau);
   hipLaunchKernelGGL(k_soft_bprep, dim3((npix + 255) / 256, pl->n), dim3(256), 0, stream,
                      pl->inv_size, lse2, d_hat, g_dhat, npix, zc, 1.f / pl->p.tau, pl->pc);
-  hipLaunchKernelGGL(k_fill_f32, dim3(1024), dim3(256), 0, stream, pl->g_half,
-                     (size_t)2 * pl->n * npix, 0.f);
   const int groups = pl->nstrips * pl->nbands * pl->n;
   const int tb = tcol_band(pl->p.arm_y);
   if (!saved) pl->wts_valid = false;  // the slabs below overwrite the weight planes
@@ -431,11 +427,13 @@ int stereo_soft_backward(stereo_ctx* c, const float* left, const float* right, i
     ta.X = X; ta.Y = Y; ta.XS = pl->XS; ta.pads = pl->pads; ta.XA = pl->XA;
     ta.npair = pl->n; ta.dlo = dlo; ta.dhi = dhi; ta.WP = pl->WP;
     ta.nstrips = pl->nstrips; ta.nbands = pl->nbands_tr;
+    ta.first = dlo == 0;  // the first slab writes every half-image gradient
     dim3 tg((unsigned)(pl->nstrips * pl->nbands_tr), (unsigned)pl->n);
     hipLaunchKernelGGL(k_soft_tr, tg, dim3(256), 0, stream, ta);
     lam_off += (size_t)tg.x * tg.y;
     hipLaunchKernelGGL(k_soft_gright, dim3((X + 255) / 256, Y, pl->n), dim3(256), 0, stream,
-                       pl->gr_part, pl->nstrips, pl->WP, dlo, dhi, X, Y, pl->g_half);
+                       pl->gr_part, pl->nstrips, pl->WP, dlo, dhi, X, Y, (int)(dlo == 0),
+                       pl->g_half);
   }
   hipLaunchKernelGGL(k_soft_gfull, dim3((W + 255) / 256, H, 2 * pl->n), dim3(256), 0, stream,
                      pl->g_half, W, H, X, Y, g_left, g_right);

@@ -8,8 +8,8 @@
 //
 //   forward   k_soft_prep   RGB float -> float half image, and the uint8 half
 //                           image of the quantised RGB (for k_feat)
-//             k_feat        census and arms (shared with the integer path)
-//             k_soft_pack   float half image + census -> padded pixel planes
+//             k_feat        census and arms (shared with the integer path),
+//                           and the padded pixel planes {float half image, census}
 //             k_soft_size   1 / |S(x,y)|, the cross-region pixel count
 //             k_soft_agg    cost C = (1 - e^{-255|dI|/lambda_AD}) +
 //                           (1 - e^{-H/lambda_census}), CA over the cross
@@ -58,32 +58,60 @@ __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_ex
 // at (2x, 2y), borders clamped.  Integer path: each channel quantised to
 // floor(255 v + 1/2) in float32 (product and sum rounded separately), clamped
 // to 0..255, then the integer gray and (sum + 4) / 9 as in k_prep.
+// The workgroup's 64 x 4 half-res pixels cover 9 x 130 full-res pixels
+// (rows 2 y0 - 1 .. 2 y0 + 7, columns 2 x0 - 1 .. 2 x0 + 128, clamped): each
+// of them is loaded once (coalesced 12-byte loads, all five of a thread
+// issued together) and its two grays go to LDS; each half-res pixel then sums
+// its block there in the order (row, column).
 // grid: (ceil(X/64), ceil(Y/4), 2n), block (64, 4).
+constexpr int kPrepTW = 130, kPrepTH = 9, kPrepTN = kPrepTW * kPrepTH;
+constexpr int kPrepLoads = (kPrepTN + 255) / 256;
+
 __global__ void __launch_bounds__(256) k_soft_prep(const float* __restrict__ left,
                                                    const float* __restrict__ right, int W, int H,
                                                    int X, int Y, float* __restrict__ half_f,
                                                    uint8_t* __restrict__ half_u8) {
-  const int x = blockIdx.x * 64 + threadIdx.x, y = blockIdx.y * 4 + threadIdx.y;
-  const int img = blockIdx.z;
-  if (x >= X || y >= Y) return;
+  __shared__ float s_f[kPrepTH][kPrepTW];
+  __shared__ int s_i[kPrepTH][kPrepTW];
+  const int t = threadIdx.y * 64 + threadIdx.x;
+  const int x0 = blockIdx.x * 64, y0 = blockIdx.y * 4, img = blockIdx.z;
   const float* rgb = ((img & 1) ? right : left) + (size_t)(img >> 1) * H * W * 3;
+  float pr[kPrepLoads][3];
+  int ti[kPrepLoads];
+#pragma unroll
+  for (int k = 0; k < kPrepLoads; ++k) {
+    ti[k] = min(t + 256 * k, kPrepTN - 1);  // past the tile: repeats its last pixel
+    const int r = ti[k] / kPrepTW, c = ti[k] - r * kPrepTW;
+    const float* p = rgb + ((size_t)clampi(2 * y0 - 1 + r, 0, H - 1) * W +
+                            clampi(2 * x0 - 1 + c, 0, W - 1)) * 3;
+    pr[k][0] = p[0];
+    pr[k][1] = p[1];
+    pr[k][2] = p[2];
+  }
+#pragma unroll
+  for (int k = 0; k < kPrepLoads; ++k) {
+    const float r = pr[k][0], g = pr[k][1], b = pr[k][2];
+    int q[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      const float v = floorf(__fadd_rn(__fmul_rn(255.f, pr[k][c]), 0.5f));
+      q[c] = (int)fminf(fmaxf(v, 0.f), 255.f);
+    }
+    const int row = ti[k] / kPrepTW, col = ti[k] - row * kPrepTW;
+    s_f[row][col] = (77.f * r + 150.f * g + 29.f * b) * (1.f / 256.f);
+    s_i[row][col] = (77 * q[0] + 150 * q[1] + 29 * q[2] + 128) >> 8;
+  }
+  __syncthreads();
+  const int lx = threadIdx.x, ly = threadIdx.y, x = x0 + lx, y = y0 + ly;
+  if (x >= X || y >= Y) return;
   float sf = 0.f;
   int si = 0;
 #pragma unroll
-  for (int j = -1; j <= 1; ++j) {
-    const float* row = rgb + (size_t)clampi(2 * y + j, 0, H - 1) * W * 3;
+  for (int j = 0; j < 3; ++j) {
 #pragma unroll
-    for (int i = -1; i <= 1; ++i) {
-      const float* p = row + (size_t)clampi(2 * x + i, 0, W - 1) * 3;
-      const float r = p[0], g = p[1], b = p[2];
-      sf += (77.f * r + 150.f * g + 29.f * b) * (1.f / 256.f);
-      int q[3];
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        const float t = floorf(__fadd_rn(__fmul_rn(255.f, p[c]), 0.5f));
-        q[c] = (int)fminf(fmaxf(t, 0.f), 255.f);
-      }
-      si += (77 * q[0] + 150 * q[1] + 29 * q[2] + 128) >> 8;
+    for (int i = 0; i < 3; ++i) {
+      sf += s_f[2 * ly + j][2 * lx + i];
+      si += s_i[2 * ly + j][2 * lx + i];
     }
   }
   const size_t o = (size_t)img * X * Y + (size_t)y * X + x;
@@ -91,52 +119,54 @@ __global__ void __launch_bounds__(256) k_soft_prep(const float* __restrict__ lef
   half_u8[o] = (uint8_t)((si + 4) / 9);
 }
 
-// ----------------------------------------------------------- k_soft_pack
-// Padded pixel planes of the soft kernels: {float half value bits, census}
-// at column pads + x of row y; the padding columns are zero (set once).
-// grid: (ceil(X/256), Y, 2n), block 256.
-__global__ void __launch_bounds__(256) k_soft_pack(const float* __restrict__ half_f,
-                                                   const uint32_t* __restrict__ pk, int X, int Y,
-                                                   int XS, int pads, uint2* __restrict__ sp) {
-  const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, img = blockIdx.z;
-  if (x >= X) return;
-  const size_t i = ((size_t)img * Y + y) * X + x;  // pk of the soft plan is unpadded
-  sp[((size_t)img * Y + y) * XS + pads + x] =
-      make_uint2(__float_as_uint(half_f[i]), (pk[i] >> 16) & 63u);
-}
-
 // ----------------------------------------------------------- k_soft_size
 // 1 / |S(x,y)| for the left image of each pair: |S| = sum over s in
 // [-M, N] of (m + n + 1) at (x, y + s) (Eq. 7-8 applied to a unit cost).
-// One workgroup = 64 columns x kSizeRows rows: the row supports m + n + 1
-// (at most 63 with arm_x <= 31) of the rows its windows reach are staged in
-// LDS as bytes, all loads issued together (rows clamped into the image; a
-// window never reaches a clamped row), and each pixel sums its window there.
+// One workgroup = 64 columns x kSizeRows rows.  The row supports m + n + 1
+// (at most 63: arm_x <= 31) of the tile rows y0 - arm_y + r, r < 144,
+// are summed down each column: wave w loads the rows 9 w .. 9 w + 8 together
+// (rows clamped into the image; a window never reaches a clamped row) and
+// keeps their running sum, the waves' totals give each wave its offset, and
+// the exclusive column prefix P (16 bits: at most 144 x 63) goes to LDS, so
+// a window is P[t + N + 1] - P[t - M], t the tile row of y.
 // grid: (ceil(X/64), ceil(Y/kSizeRows), n), block (64, kSizeRows).
-constexpr int kSizeRows = 16, kSizeMaxArm = 63;
-constexpr int kSizeLoads = (kSizeRows + 2 * kSizeMaxArm + kSizeRows - 1) / kSizeRows;
+constexpr int kSizeRows = 16, kSizeMaxArm = 63, kSizeSeg = 9;
+static_assert(kSizeRows * kSizeSeg >= kSizeRows + 2 * kSizeMaxArm, "tile rows");
 
 __global__ void __launch_bounds__(64 * kSizeRows) k_soft_size(const uint32_t* __restrict__ arms,
                                                              int X, int Y, int XA, int arm_y,
                                                              float* __restrict__ inv_size) {
-  __shared__ uint8_t h[kSizeLoads * kSizeRows][64];
+  __shared__ uint16_t s_p[kSizeRows * kSizeSeg + 1][64];
+  __shared__ uint16_t s_t[kSizeRows][64];
   const int x0 = blockIdx.x * 64, y0 = blockIdx.y * kSizeRows, pair = blockIdx.z;
   const int lx = threadIdx.x, ly = threadIdx.y, x = x0 + lx;  // x < XA: zero padding past X
   const uint32_t* a = arms + (size_t)(2 * pair) * Y * XA;
-  uint32_t v[kSizeLoads];
-#pragma unroll
-  for (int k = 0; k < kSizeLoads; ++k)
-    v[k] = a[(size_t)clampi(y0 - arm_y + ly + kSizeRows * k, 0, Y - 1) * XA + x];
-#pragma unroll
-  for (int k = 0; k < kSizeLoads; ++k)
-    h[ly + kSizeRows * k][lx] = (uint8_t)((v[k] & 255u) + ((v[k] >> 8) & 255u) + 1u);
-  __syncthreads();
   const int y = y0 + ly;
+  uint32_t c = a[(size_t)min(y, Y - 1) * XA + x];
+  uint32_t v[kSizeSeg];
+#pragma unroll
+  for (int k = 0; k < kSizeSeg; ++k)
+    v[k] = a[(size_t)clampi(y0 - arm_y + kSizeSeg * ly + k, 0, Y - 1) * XA + x];
+  // the pixel's own arms stay loaded with the tile's (not after the barriers)
+  __asm__ volatile("" : "+v"(c));
+  uint32_t run = 0, loc[kSizeSeg];
+#pragma unroll
+  for (int k = 0; k < kSizeSeg; ++k) {
+    run += (v[k] & 255u) + ((v[k] >> 8) & 255u) + 1u;
+    loc[k] = run;
+  }
+  s_t[ly][lx] = (uint16_t)run;
+  __syncthreads();
+  uint32_t off = 0;
+#pragma unroll
+  for (int l = 0; l < kSizeRows; ++l) off += l < ly ? (uint32_t)s_t[l][lx] : 0u;
+#pragma unroll
+  for (int k = 0; k < kSizeSeg; ++k) s_p[kSizeSeg * ly + k + 1][lx] = (uint16_t)(off + loc[k]);
+  if (ly == 0) s_p[0][lx] = 0;
+  __syncthreads();
   if (x >= X || y >= Y) return;
-  const uint32_t c = a[(size_t)y * XA + x];
   const int M = (c >> 16) & 255, N = c >> 24, t = ly + arm_y;  // tile row of y
-  int sum = 0;
-  for (int r = t - M; r <= t + N; ++r) sum += h[r][lx];
+  const int sum = (int)s_p[t + N + 1][lx] - (int)s_p[t - M][lx];
   inv_size[(size_t)pair * X * Y + (size_t)y * X + x] = 1.f / (float)sum;
 }
 
@@ -695,7 +725,8 @@ __global__ void __launch_bounds__(64 * kTcwWaves) k_soft_tcolw(
 // point with a per-row scale (as in k_soft_tcol: terms below 2^23, sums of
 // at most 63 terms below 2^29), added with LDS integer atomics, so the
 // result does not depend on their order.  The left gradient of a pixel stays
-// in a register over the slab and is added to g_half once; the right one, at
+// in a register over the slab and goes to g_half once (written by the first
+// slab, added by the others); the right one, at
 // column x - d, goes to the wave's LDS row (one writer per entry and
 // disparity, disparities in order) and then to this strip's partial row,
 // which k_soft_gright sums over the strips.  The horizontal arms and the
@@ -706,10 +737,11 @@ struct TrArgs {
   const uint32_t* arms;     // [2n][Y][XA]
   const uint2* sp;          // [2n][Y][XS] padded pixel planes
   const float* lam;         // device [2]
-  float* g_half;            // [2n][Y][X] half-image gradients (left ones added here)
+  float* g_half;            // [2n][Y][X] half-image gradients (left ones written or added here)
   float* gr_part;           // [n][strips][Y][WP] -dL/dR partials of this slab
   float2* lam_part;         // one {d/dlambda_AD, d/dlambda_census} per workgroup
   int X, Y, XS, pads, XA, npair, dlo, dhi, nstrips, nbands, WP;
+  int first;                // first slab: the left gradients are written, not added
 };
 
 // Inclusive maximum scan over the 64 lanes of a wave of values >= 0 (the
@@ -917,7 +949,8 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
     process_d(d + 1, in1);
   }
   WAVE_LDS_ORDER();
-  // left gradients: each pixel has one owner; slabs run one after another
+  // left gradients: each pixel has one owner (so the first slab writes every
+  // one); slabs run one after another
   float* glp = a.g_half + (size_t)(2 * pair) * plane;
   // right partials of this strip: columns x0 - dhi + 1 .. x0 + 63 - dlo
   const int wd = 64 + (a.dhi - a.dlo) - 1;
@@ -926,7 +959,10 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
   for (int i = 0; i < RPW; ++i) {
     if (!yv[i]) continue;
     const int y = ys[i], r = wave + 4 * i;
-    if (xin) glp[(size_t)y * X + x] += gl[i];
+    if (xin) {
+      float* g = glp + (size_t)y * X + x;
+      *g = a.first ? gl[i] : *g + gl[i];
+    }
     for (int c = lane; c < wd; c += 64) gp[(size_t)y * a.WP + c] = s_gr[r][c];
   }
   // fixed-order reduction of the lambda partials over the workgroup
@@ -947,11 +983,12 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
 // --------------------------------------------------------- k_soft_gright
 // dL/dR(x,y) over a slab [dlo, dhi): the partials of the strips s whose
 // columns x + d (d in the slab) reach, floor((x + dlo) / 64) ..
-// floor((x + dhi - 1) / 64), summed in strip order, added to g_half.
+// floor((x + dhi - 1) / 64), summed in strip order, written to g_half for the
+// first slab and added to it for the others.
 // grid: (ceil(X/256), Y, n), block 256.
 __global__ void __launch_bounds__(256) k_soft_gright(const float* __restrict__ gr_part, int nstrips,
                                                      int WP, int dlo, int dhi, int X, int Y,
-                                                     float* __restrict__ g_half) {
+                                                     int first, float* __restrict__ g_half) {
   const int x = blockIdx.x * 256 + threadIdx.x, y = blockIdx.y, pair = blockIdx.z;
   if (x >= X) return;
   const int s0 = (x + dlo) / 64, s1 = min(nstrips - 1, (x + dhi - 1) / 64);
@@ -960,36 +997,40 @@ __global__ void __launch_bounds__(256) k_soft_gright(const float* __restrict__ g
     const int c = x - (s * 64 - dhi + 1);  // in 0 .. WP - 1 for the strips reached
     acc += gr_part[(((size_t)pair * nstrips + s) * Y + y) * WP + c];
   }
-  g_half[((size_t)(2 * pair + 1) * Y + y) * X + x] += acc;
+  float* g = g_half + ((size_t)(2 * pair + 1) * Y + y) * X + x;
+  *g = first ? acc : *g + acc;
 }
 
 // ---------------------------------------------------------- k_soft_gfull
 // dL/d(RGB) from dL/d(half image): a full-res pixel (u, v) receives g/9 from
 // every half-res pixel whose clamped 3x3 block holds it, once per block cell
 // that lands on it, times the channel's gray weight (77, 150, 29) / 256.
+// Along each axis those pixels are among p >> 1 and (p + 1) >> 1 (the latter
+// only for odd p inside the image), with weight #{j in -1..1 :
+// clamp(2 q + j) = p}: the four loads are unconditional (indices clamped, a
+// repeated index gets weight 0).
 // grid: (ceil(W/256), H, 2n), block 256.
+__device__ __forceinline__ int gfull_weight(int q, int p, int lim) {
+  int w = 0;
+#pragma unroll
+  for (int j = -1; j <= 1; ++j) w += clampi(2 * q + j, 0, lim - 1) == p;
+  return w;
+}
+
 __global__ void __launch_bounds__(256) k_soft_gfull(const float* __restrict__ g_half, int W, int H,
                                                     int X, int Y, float* __restrict__ g_left,
                                                     float* __restrict__ g_right) {
   const int u = blockIdx.x * 256 + threadIdx.x, v = blockIdx.y, img = blockIdx.z;
   if (u >= W) return;
   const float* gh = g_half + (size_t)img * X * Y;
-  float acc = 0.f;
-  const int yl = max(0, (v - 1) >> 1), yh = min(Y - 1, (v + 2) >> 1);
-  const int xl = max(0, (u - 1) >> 1), xh = min(X - 1, (u + 2) >> 1);
-  for (int y = yl; y <= yh; ++y) {
-    int wy = 0;
-#pragma unroll
-    for (int j = -1; j <= 1; ++j) wy += clampi(2 * y + j, 0, H - 1) == v;
-    if (!wy) continue;
-    for (int x = xl; x <= xh; ++x) {
-      int wx = 0;
-#pragma unroll
-      for (int i = -1; i <= 1; ++i) wx += clampi(2 * x + i, 0, W - 1) == u;
-      if (wx) acc += (float)(wx * wy) * gh[(size_t)y * X + x];
-    }
-  }
-  acc *= 1.f / (9.f * 256.f);
+  const int ya = v >> 1, yb = min((v + 1) >> 1, Y - 1);
+  const int xa = u >> 1, xb = min((u + 1) >> 1, X - 1);
+  const float g00 = gh[(size_t)ya * X + xa], g01 = gh[(size_t)ya * X + xb];
+  const float g10 = gh[(size_t)yb * X + xa], g11 = gh[(size_t)yb * X + xb];
+  const float wya = (float)gfull_weight(ya, v, H), wyb = yb != ya ? (float)gfull_weight(yb, v, H) : 0.f;
+  const float wxa = (float)gfull_weight(xa, u, W), wxb = xb != xa ? (float)gfull_weight(xb, u, W) : 0.f;
+  const float acc = (wya * (wxa * g00 + wxb * g01) + wyb * (wxa * g10 + wxb * g11)) *
+                    (1.f / (9.f * 256.f));
   float* out = ((img & 1) ? g_right : g_left) + ((size_t)(img >> 1) * H * W + (size_t)v * W + u) * 3;
   out[0] = 77.f * acc;
   out[1] = 150.f * acc;
@@ -1046,62 +1087,91 @@ __global__ void k_fill_f32(float* __restrict__ p, size_t n, float v) {
 // L = (1/n) sum over pairs of mean over {(x,y): nonocc(2x,2y)} of
 // |2 d_hat(x,y) - GT(2x,2y)|; dL/dd_hat = 2 sign(2 d_hat - GT) / (n count)
 // there (sign(0) = 0), 0 elsewhere.
-// k_l1_partial grid: (nblk, n), block 256; partial sums per block.
+// k_l1_partial grid: (nblk, n), block 256; partial sums per block.  Block b
+// takes the rows b, b + nblk, ...; each thread four columns of a row at a
+// time, their loads issued together (columns past X clamped, then not
+// counted); a fixed-order reduction over the block.
 __global__ void __launch_bounds__(256) k_l1_partial(const float* __restrict__ dhat,
                                                     const int16_t* __restrict__ gt,
                                                     const uint8_t* __restrict__ nonocc, int W,
                                                     int H, int X, int Y,
                                                     float2* __restrict__ part) {
-  __shared__ float2 s[256];
+  __shared__ float2 s[4];
   const int t = threadIdx.x, pair = blockIdx.y;
   const int npix = X * Y;
   float sum = 0.f, cnt = 0.f;
-  // block b takes the rows b, b + nblk, ...; its threads the columns
   for (int y = blockIdx.x; y < Y; y += gridDim.x) {
     const size_t fr = (size_t)pair * H * W + (size_t)(2 * y) * W;
     const float* dr = dhat + (size_t)pair * npix + (size_t)y * X;
-    for (int x = t; x < X; x += 256) {
-      if (nonocc[fr + 2 * x]) {
-        sum += fabsf(2.f * dr[x] - (float)gt[fr + 2 * x]);
-        cnt += 1.f;
+    for (int x0 = 0; x0 < X; x0 += 4 * 256) {
+      float dv[4];
+      int gv[4];
+      uint32_t mv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int x = min(x0 + t + 256 * k, X - 1);
+        dv[k] = dr[x];
+        gv[k] = gt[fr + 2 * x];
+        mv[k] = nonocc[fr + 2 * x];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const bool use = x0 + t + 256 * k < X && mv[k] != 0u;
+        sum += use ? fabsf(2.f * dv[k] - (float)gv[k]) : 0.f;
+        cnt += use ? 1.f : 0.f;
       }
     }
   }
-  s[t] = make_float2(sum, cnt);
-  __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (t < o) {
-      s[t].x += s[t + o].x;
-      s[t].y += s[t + o].y;
-    }
-    __syncthreads();
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    sum += __shfl_xor(sum, o, 64);
+    cnt += __shfl_xor(cnt, o, 64);
   }
-  if (t == 0) part[(size_t)pair * gridDim.x + blockIdx.x] = s[0];
+  if ((t & 63) == 0) s[t >> 6] = make_float2(sum, cnt);
+  __syncthreads();
+  if (t == 0) {
+    float2 r = s[0];
+    for (int w = 1; w < 4; ++w) {
+      r.x += s[w].x;
+      r.y += s[w].y;
+    }
+    part[(size_t)pair * gridDim.x + blockIdx.x] = r;
+  }
 }
 
-// k_l1_final grid: 1, block 64: loss and the per-pair counts.  Lane b sums
-// the blocks b, b + 64, ... of a pair, then a butterfly over the lanes (a
-// fixed order: the result does not depend on scheduling).
-__global__ void __launch_bounds__(64) k_l1_final(const float2* __restrict__ part, int nblk,
-                                                 int npair, float* __restrict__ loss,
-                                                 float* __restrict__ counts) {
-  const int lane = threadIdx.x;
-  float total = 0.f;
-  for (int p = 0; p < npair; ++p) {
+// k_l1_final grid: 1, block 256: loss and the per-pair counts.  Wave w takes
+// the pairs w, w + 4, ...: lane b sums the blocks b, b + 64, ... of a pair,
+// then a butterfly over the lanes; the per-pair means are summed in pair
+// order (a fixed order: the result does not depend on scheduling).
+__global__ void __launch_bounds__(256) k_l1_final(const float2* __restrict__ part, int nblk,
+                                                  int npair, float* __restrict__ loss,
+                                                  float* __restrict__ counts) {
+  __shared__ float s_mean[64];  // npair <= 64
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int p = wave; p < npair; p += 4) {
     float s = 0.f, c = 0.f;
+#pragma unroll 4
     for (int b = lane; b < nblk; b += 64) {
-      s += part[(size_t)p * nblk + b].x;
-      c += part[(size_t)p * nblk + b].y;
+      const float2 v = part[(size_t)p * nblk + b];
+      s += v.x;
+      c += v.y;
     }
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
       s += __shfl_xor(s, o, 64);
       c += __shfl_xor(c, o, 64);
     }
-    if (lane == 0) counts[p] = c;
-    total += s / fmaxf(c, 1.f);
+    if (lane == 0) {
+      counts[p] = c;
+      s_mean[p] = s / fmaxf(c, 1.f);
+    }
   }
-  if (lane == 0) *loss = total / (float)npair;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float total = 0.f;
+    for (int p = 0; p < npair; ++p) total += s_mean[p];
+    *loss = total / (float)npair;
+  }
 }
 
 // k_l1_grad grid: (ceil(X*Y/256), n), block 256.
@@ -1117,14 +1187,15 @@ __global__ void __launch_bounds__(256) k_l1_grad(const float* __restrict__ dhat,
   if (i >= npix) return;
   const int y = i / X, x = i - y * X;
   const size_t f = (size_t)pair * H * W + (size_t)(2 * y) * W + 2 * x;
-  float g = 0.f;
-  if (nonocc[f]) {
-    const float r = 2.f * dhat[(size_t)pair * npix + i] - (float)gt[f];
-    const float sg = r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f);
-    g = 2.f * sg / (fmaxf(counts[pair], 1.f) * (float)npair);
-    if (gscale) g *= *gscale;
-  }
-  g_dhat[(size_t)pair * npix + i] = g;
+  // all loads issued together, the mask applied after
+  const uint8_t m = nonocc[f];
+  const float dv = dhat[(size_t)pair * npix + i], gv = (float)gt[f];
+  const float cnt = counts[pair], sc = gscale ? *gscale : 1.f;
+  const float r = 2.f * dv - gv;
+  const float sg = r > 0.f ? 1.f : (r < 0.f ? -1.f : 0.f);
+  float g = 2.f * sg / (fmaxf(cnt, 1.f) * (float)npair);
+  if (gscale) g *= sc;
+  g_dhat[(size_t)pair * npix + i] = m ? g : 0.f;
 }
 
 }  // namespace

@@ -522,7 +522,7 @@ int run(stereo_ctx* c, Plan& pl, const PairPtrs& pp, int npair, bool keep, bool 
   hipLaunchKernelGGL(k_feat, dim3((X + 63) / 64, (Y + kFeatRows - 1) / kFeatRows, 2 * npair),
                      dim3(64, kFeatRows), 0,
                      s, pl.half, X, Y, pl.p.color_delta, pl.p.arm_x, pl.p.arm_x_r, pl.p.arm_y,
-                     pl.XP, pl.pad, pl.XA, nullptr, pl.arms, pl.xoff, pl.pk,
+                     pl.XP, pl.pad, pl.XA, nullptr, nullptr, pl.arms, pl.xoff, pl.pk,
                      (size_t)2 * npair * Y * pl.XP);
   mark(2);
   launch_match(pl, match_args(pl, 0, pl.D, pl.csize), npair, s);
