@@ -756,22 +756,21 @@ __device__ __forceinline__ int wave_max_scan_incl(int v) {
   return v;
 }
 
-// Maximum over the 64 lanes of a wave, in every lane.
-__device__ __forceinline__ float wave_max_f(float v) {
-  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x128, 0xf, 0xf, false)));  // row_ror:8
-  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x124, 0xf, 0xf, false)));  // row_ror:4
-  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4e, 0xf, 0xf, false)));   // quad_perm 2,3,0,1
-  v = fmaxf(v, __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xb1, 0xf, 0xf, false)));   // quad_perm 1,0,3,2
-  const float a = fmaxf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0)),
-                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16)));
-  const float b = fmaxf(__int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 32)),
-                        __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 48)));
-  return fmaxf(a, b);
+// Maximum over the 64 lanes of a wave (row rotations inside rows of 16
+// lanes, then row broadcasts; lane 63 ends with the maximum of all).
+__device__ __forceinline__ uint32_t wave_max_u32(uint32_t v) {
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x128, 0xf, 0xf, false));  // row_ror:8
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x124, 0xf, 0xf, false));  // row_ror:4
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4e, 0xf, 0xf, false));   // quad_perm 2,3,0,1
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xb1, 0xf, 0xf, false));   // quad_perm 1,0,3,2
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xa, 0xf, false));  // row_bcast:15
+  v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xc, 0xf, false));  // row_bcast:31
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 constexpr int kTrMaxWP = 64 + 127;  // 64 columns + a slab of up to 128 disparities
 
-__global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_soft_tr(TrArgs a) {
   constexpr int BR = kSoftBR;
   static_assert(BR == 16, "four band rows per wave");
   constexpr int RPW = BR / 4;  // rows per wave: r = wave + 4 i
@@ -810,14 +809,27 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
     gl[i] = 0.f;
     for (int c = lane; c < kTrMaxWP; c += 64) s_gr[wave + 4 * i][c] = 0.f;
   }
-  // The two main updates of a row's difference array, -q at the right end
-  // hi of the sources left of the strip (h = 0) and +q at the left end lo of
-  // those right of it (h = 1), repeat a position over runs of neighbouring
-  // lanes whose arms stop at the same edge; such a run would serialise its
-  // atomics on one address.  The runs do not depend on d: per source and row,
-  // the lane where its run starts, whether it ends the run, and its position.
-  // Per d one wave scan gives each run's sum, added by the run's last lane.
-  uint32_t run[RPW][2];
+  // Each source adds +q at the left end of its window (its position clamped
+  // to the strip's first column) and -q after the right end (when that is
+  // inside the strip).  Neighbouring sources whose windows end at the same
+  // edge form runs of lanes with the same position, which would serialise
+  // their atomics on one address.  The runs do not depend on d: per row,
+  // source set h and end, 16 bits give the lane before the run's first
+  // (bits 0..7, as a ds_bpermute address) and whether it exists (bit 8),
+  // whether this lane ends a run of contributing sources (bit 9) and the
+  // position (bits 10..15); the left end's in the low half of a word, the
+  // right end's in the high half.  Per d and source set one wave scan of the
+  // terms serves both ends: each run's sum is the scan at its last lane
+  // minus the scan before its first, added (left ends) or subtracted (right
+  // ends) by its last lane.
+  uint32_t rw[RPW][2];
+  auto run_word = [&](int key, bool ends, int pos) -> uint32_t {
+    const int kp = __builtin_amdgcn_update_dpp(1000, key, 0x138, 0xf, 0xf, false);  // wave_shr:1
+    const int kn = __builtin_amdgcn_update_dpp(1000, key, 0x130, 0xf, 0xf, false);  // wave_shl:1
+    const int hs = wave_max_scan_incl(key != kp ? lane : 0);  // first lane of the run
+    return (uint32_t)(max(hs - 1, 0) * 4) | (hs > 0 ? 256u : 0u) |
+           (ends && key != kn ? 512u : 0u) | (uint32_t)(pos & 63) << 10;
+  };
 #pragma unroll
   for (int i = 0; i < RPW; ++i) {
 #pragma unroll
@@ -825,13 +837,13 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
       const int col = x0 - 32 + 64 * h + lane;
       const int lo = col - (int)(mv[i][h] & 255u) - x0;
       const int hi = col + (int)((mv[i][h] >> 8) & 255u) + 1 - x0;
+      // the window reaches the strip (lo < 64 for h = 0 and hi > 0 for h = 1
+      // always hold with arm_x <= 31)
       const bool part = cv[i][h] && (h == 0 ? hi > 0 : lo < 64);
-      const int pos = h == 0 ? hi : lo;
-      const int key = part ? pos : -1 - lane;
-      const int kp = __builtin_amdgcn_update_dpp(1000, key, 0x138, 0xf, 0xf, false);  // wave_shr:1
-      const int kn = __builtin_amdgcn_update_dpp(1000, key, 0x130, 0xf, 0xf, false);  // wave_shl:1
-      const int hs = wave_max_scan_incl(key != kp ? lane : 0);
-      run[i][h] = (uint32_t)hs | (part && key != kn ? 256u : 0u) | (uint32_t)(pos & 63) << 9;
+      const int plo = max(lo, 0);
+      const bool phi = part && hi < 64;
+      rw[i][h] = run_word(part ? plo : -1 - lane, part, plo) |
+                 run_word(phi ? hi : -1 - lane, phi, hi) << 16;
     }
   }
   const float lam_ad = a.lam[0], lam_c = a.lam[1];
@@ -871,49 +883,31 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
     for (int i = 0; i < RPW; ++i) s_d[wave + 4 * i][lane] = 0;
     WAVE_LDS_ORDER();
     float down[RPW];
-    // sum of the terms whose window starts at or left of the strip's first
-    // column (all of them would add to entry 0: one wave sum instead of up to
-    // 64 atomics on one address), added to lane 0 before the row's scan
-    int qz[RPW];
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
+      const int r = wave + 4 * i;
       const float g0 = cv[i][0] ? in.g[i][0] : 0.f, g1 = cv[i][1] ? in.g[i][1] : 0.f;
-      int qc = 0;
-      const float mx = wave_max_f(fmaxf(fabsf(g0), fabsf(g1)));
-      int e = 0;
-      (void)frexpf(mx, &e);
-      const float up = mx > 0.f ? ldexpf(1.f, 23 - e) : 0.f;
-      down[i] = mx > 0.f ? ldexpf(1.f, e - 23) : 0.f;
-      int vr[2] = {0, 0};  // this lane's term of the run update of h = 0, 1
+      // the row's scale 2^(23 - e), 2^(e - 1) <= max |g| < 2^e (frexp's e),
+      // from the largest magnitude's bits (the bit order of floats >= 0)
+      const uint32_t mb = wave_max_u32(max(__float_as_uint(g0) & 0x7fffffffu,
+                                           __float_as_uint(g1) & 0x7fffffffu));
+      const int be = (int)(mb >> 23);
+      const int e = be > 0 ? be - 126 : -117 - (int)__builtin_clz(mb | 1u);
+      const float up = mb ? ldexpf(1.f, 23 - e) : 0.f;
+      down[i] = mb ? ldexpf(1.f, e - 23) : 0.f;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        const float gvh = h ? g1 : g0;
-        if (gvh != 0.f) {
-          const int q = (int)rintf(gvh * up);
-          const int col = x0 - 32 + 64 * h + lane;
-          const int lo = col - (int)(mv[i][h] & 255u) - x0;
-          const int hi = col + (int)((mv[i][h] >> 8) & 255u) + 1 - x0;
-          if (hi > 0 && lo < 64) {
-            if (h == 0) {
-              vr[0] = -q;  // at hi (always < 64 here)
-              if (lo <= 0) qc += q;
-              else atomicAdd(&s_d[wave + 4 * i][lo], q);
-            } else {
-              vr[1] = q;   // at lo (always >= 1 here)
-              if (hi < 64) atomicAdd(&s_d[wave + 4 * i][hi], -q);
-            }
-          }
-        }
+        // the fields of the run words are taken apart here, per d (held
+        // over the loop, they took more registers than the kernel has)
+        __asm__ volatile("" : "+v"(rw[i][h]));
+        const int q = (int)rintf((h ? g1 : g0) * up);
+        const int P = (int)wave_scan_incl((uint32_t)q);
+        const uint32_t w = rw[i][h];
+        const int Pl = __builtin_amdgcn_ds_bpermute((int)(w & 255u), P);
+        const int Ph = __builtin_amdgcn_ds_bpermute((int)((w >> 16) & 255u), P);
+        if (w & (512u << 16)) atomicSub(&s_d[r][w >> 26], P - ((w & (256u << 16)) ? Ph : 0));
+        if (w & 512u) atomicAdd(&s_d[r][(w >> 10) & 63u], P - ((w & 256u) ? Pl : 0));
       }
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int P = (int)wave_scan_incl((uint32_t)vr[h]);
-        const int hs = (int)(run[i][h] & 255u);
-        const int Pm = __builtin_amdgcn_ds_bpermute(max(hs - 1, 0) * 4, P);
-        if (run[i][h] & 256u)
-          atomicAdd(&s_d[wave + 4 * i][run[i][h] >> 9], P - (hs > 0 ? Pm : 0));
-      }
-      qz[i] = (int)__builtin_amdgcn_readlane(wave_scan_incl((uint32_t)qc), 63);
     }
     WAVE_LDS_ORDER();
     // prefix along each row, then the cost derivatives; the right gradient
@@ -922,8 +916,7 @@ __global__ void __launch_bounds__(256) k_soft_tr(TrArgs a) {
 #pragma unroll
     for (int i = 0; i < RPW; ++i) {
       const int r = wave + 4 * i;
-      const int dz = s_d[r][lane] + (lane == 0 ? qz[i] : 0);
-      const float gc = (float)(int)wave_scan_incl((uint32_t)dz) * down[i];
+      const float gc = (float)(int)wave_scan_incl((uint32_t)s_d[r][lane]) * down[i];
       if (xin && dv && yv[i]) {
         const float di = __uint_as_float(pl_[i].x) - __uint_as_float(in.pr[i].x);
         const float ad = fabsf(di);
