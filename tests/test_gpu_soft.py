@@ -182,9 +182,10 @@ def test_backward_is_deterministic_and_batch_matches_single(ctx):
     L, R, G, M = float_pairs(3, 96, 40, 30, 550, noise=0.002)
     p = osoft.SoftParams()
     a = run_gpu(ctx, L, R, G, M, 30, p)
-    b = run_gpu(ctx, L, R, G, M, 30, p)
-    for u, v in zip(a, b):
-        assert np.array_equal(np.asarray(u), np.asarray(v))
+    for rep in range(9):  # ten runs in all, the same bits each time
+        b = run_gpu(ctx, L, R, G, M, 30, p)
+        for u, v in zip(a, b):
+            assert np.array_equal(np.asarray(u), np.asarray(v)), rep
     # pair 1 alone: same d_hat (chunk sums may group differently) and, with the
     # loss of one pair instead of the mean of three, 3x the image gradients
     s = run_gpu(ctx, L[1:2], R[1:2], G[1:2], M[1:2], 30, p)
@@ -202,6 +203,24 @@ def launch_step(ctx, L, R, G, M, dmax, p):
     loss = l1_loss(ctx, d_hat, to_dev(G.astype(np.int16)), to_dev(M.astype(np.uint8)))
     loss.backward()
     return d_hat, loss, left, right, lambdas
+
+
+def test_ten_training_steps_bit_identical_at_paper_size(ctx):
+    """4 x 1436x992, Dmax = 145: ten forward + loss + backward steps (the
+    saved-weights path) give the same d_hat, loss and gradients bit for bit."""
+    L, R, G, M = float_pairs(4, 1436, 992, 145, 400)
+    p = osoft.SoftParams()
+    first = None
+    for rep in range(10):
+        d_hat, loss, left, right, lam = launch_step(ctx, L, R, G, M, 145, p)
+        torch.cuda.synchronize()
+        got = (d_hat.detach().cpu().numpy(), loss.detach().cpu().numpy(),
+               left.grad.cpu().numpy(), right.grad.cpu().numpy(), lam.grad.cpu().numpy())
+        if first is None:
+            first = got
+            continue
+        for u, v in zip(got, first):
+            assert np.array_equal(u, v), rep
 
 
 def test_two_streams_equal_serial_runs(ctx):
