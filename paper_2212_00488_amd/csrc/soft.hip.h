@@ -48,7 +48,7 @@ namespace stereo_dev {
 // carries its own copy (no relocatable device code).
 namespace {
 
-constexpr int kSoftBR = 16;  // output rows per k_soft_tr workgroup
+constexpr int kSoftBR = 4;  // output rows per k_soft_tr workgroup (one per wave)
 
 __device__ __forceinline__ float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
 
@@ -717,17 +717,21 @@ __global__ void __launch_bounds__(64 * kTcwWaves) k_soft_tcolw(
 // for x - d >= 0 (the constant cost of x - d < 0 has no derivative).
 // The sources of a row are the columns x0 - 32 .. x0 + 95 (every column
 // whose horizontal window reaches the strip, arm_x <= 31).  Wave w owns the
-// band rows w, w + 4, w + 8, w + 12 entirely: lane l loads source columns
-// x0 - 32 + l and x0 + 32 + l of them (coalesced), scatters them into the
-// rows' difference arrays, scans the rows and takes the derivatives at
-// output column x0 + l, so the disparity loop needs no barrier (a wave's LDS
+// band rows w + 4 i, i < kSoftBR / 4 (one row with bands of 4: 51 VGPRs, 8
+// waves per SIMD, and the grid of 5952 workgroups at the paper's size takes
+// 2.9 rounds; bands of 16 rows took 120 VGPRs and 1.45 rounds, and ran
+// slower than bands of 8, which ran slower than bands of 4): lane l loads
+// source columns x0 - 32 + l and x0 + 32 + l of them (coalesced), scatters
+// them into the rows' difference arrays, scans the rows and takes the
+// derivatives at output column x0 + l, so the disparity loop needs no
+// barrier (a wave's LDS
 // accesses are served in order).  The difference arrays are integer fixed
 // point with a per-row scale (as in k_soft_tcol: terms below 2^23, sums of
 // at most 63 terms below 2^29), added with LDS integer atomics, so the
 // result does not depend on their order.  The left gradient of a pixel stays
 // in a register over the slab and goes to g_half once (written by the first
-// slab, added by the others); the right one, at
-// column x - d, goes to the wave's LDS row (one writer per entry and
+// slab, added by the others); the right one, at column x - d, goes to the
+// wave's LDS row (one writer per entry and
 // disparity, disparities in order) and then to this strip's partial row,
 // which k_soft_gright sums over the strips.  The horizontal arms and the
 // left pixels do not depend on d and are loaded once.
@@ -772,7 +776,7 @@ constexpr int kTrMaxWP = 64 + 127;  // 64 columns + a slab of up to 128 disparit
 
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k_soft_tr(TrArgs a) {
   constexpr int BR = kSoftBR;
-  static_assert(BR == 16, "four band rows per wave");
+  static_assert(BR % 4 == 0, "whole rows per wave");
   constexpr int RPW = BR / 4;  // rows per wave: r = wave + 4 i
   __shared__ int s_d[BR][64];
   __shared__ float s_gr[BR][kTrMaxWP];
