@@ -1,5 +1,6 @@
 """Host logic of bench.py (CPU): the one-GPU refusal, the code hash that keys
-the committed traffic counters, and the percentile used for the latency."""
+the committed traffic counters, the percentile used for the latency, and the
+pre-warm loop."""
 
 import json
 import os
@@ -52,3 +53,17 @@ def test_traffic_is_null_once_the_source_changes(monkeypatch):
 @pytest.mark.parametrize("q,expected", [(0, 1.0), (50, 3.0), (100, 5.0), (99, 5.0)])
 def test_percentile(q, expected):
     assert bench.percentile([5.0, 1.0, 4.0, 2.0, 3.0], q) == expected
+
+
+def test_prewarm_repeats_the_work_for_its_duration(monkeypatch):
+    """The pre-warm runs the work in groups of sync_every calls, one device
+    synchronisation after each group, until its time has passed; 0 ms runs
+    nothing."""
+    torch = pytest.importorskip("torch")
+    syncs = []
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: syncs.append(1))
+    calls = []
+    bench.prewarm(lambda: calls.append(1), 0.0, 4)
+    assert calls == [] and syncs == []
+    bench.prewarm(lambda: calls.append(1), 20.0, 4)
+    assert len(calls) >= 4 and len(calls) == 4 * len(syncs)
