@@ -781,6 +781,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   __shared__ int s_d[BR][64];
   __shared__ float s_gr[BR][kTrMaxWP];
   __shared__ float2 s_red[4];
+  __shared__ float s_hc[4][8];  // per wave: the census term of dC/dlambda_census by h
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int strip = blockIdx.x % a.nstrips, band = blockIdx.x / a.nstrips;
   const int pair = blockIdx.y;
@@ -854,6 +855,10 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
   const float k2 = 255.f * 1.4426950408889634f / lam_ad;
   const float kt = 255.f / lam_ad, ka = 1.f / (lam_ad * lam_ad), kc = 1.f / (lam_c * lam_c);
   const float l2c = 1.4426950408889634f / lam_c;
+  // -e^{-h/lambda_census} h / lambda_census^2 for h = 0..6, one copy per wave
+  // (a wave's LDS accesses are served in order: no barrier)
+  if (lane < 7) s_hc[wave][lane] = -fast_exp2(-(float)lane * l2c) * (float)lane * kc;
+  WAVE_LDS_ORDER();
   float pa = 0.f, pcs = 0.f;
   // the loads of disparity d + 1 are issued before d is processed (two
   // register sets used in turn; the last disparity is reloaded past the end,
@@ -931,7 +936,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
         s_gr[r][gcol] -= tv;
         pa += gc * (-E * 255.f * ad * ka);
         const int hh = __builtin_popcount(pl_[i].y ^ in.pr[i].y);
-        pcs += gc * (-fast_exp2(-(float)hh * l2c) * (float)hh * kc);
+        pcs += gc * s_hc[wave][hh];
       }
     }
     WAVE_LDS_ORDER();
