@@ -906,9 +906,6 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) k
       down[i] = mb ? ldexpf(1.f, e - 23) : 0.f;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
-        // the fields of the run words are taken apart here, per d (held
-        // over the loop, they took more registers than the kernel has)
-        __asm__ volatile("" : "+v"(rw[i][h]));
         const int q = (int)rintf((h ? g1 : g0) * up);
         const int P = (int)wave_scan_incl((uint32_t)q);
         const uint32_t w = rw[i][h];
